@@ -1,0 +1,433 @@
+"""Pins of the oracle against the paper and against mathematics (no GPU).
+
+Each test ties an oracle function to something other than itself: an algebraic
+identity the paper states, a closed form, a library routine, a hand-derived fixture,
+or a statistical law.  A plausible mistake (dropped term, wrong sign or index,
+transposed operand) in the oracle fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import dense, ensemble, haar, matfree, pauli, splitmix
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------- Majoranas
+@pytest.mark.parametrize("N", [6, 8, 10, 12, 14])
+def test_clifford_algebra(N):
+    """{chi_m, chi_n} = delta_mn (main text, Clifford algebra below Eq. (1))."""
+    ch = dense.chis(N)
+    d = ch[0].shape[0]
+    for m in range(N):
+        for n in range(N):
+            ac = ch[m] @ ch[n] + ch[n] @ ch[m]
+            ref = np.eye(d) if m == n else np.zeros((d, d))
+            assert np.abs(ac - ref).max() < 1e-15
+        assert np.allclose(ch[m], ch[m].conj().T)
+
+
+@pytest.mark.parametrize("N", [6, 10, 14])
+def test_block_forms_stated_in_supplement(N):
+    """Majoranas are block off-diagonal; gamma_{N-1}^UD = -gamma_{N-1}^DU = -i 1 and
+    gamma_{N-2}^UD = gamma_{N-2}^DU = sigma_z on block qubit N/2-2 (supplement, Sec. I)."""
+    g = dense.gammas(N)
+    d = g[0].shape[0]
+    h = d // 2
+    L = N // 2 - 1
+    for gn in g:
+        assert np.abs(gn[:h, :h]).max() == 0 and np.abs(gn[h:, h:]).max() == 0
+    assert np.array_equal(g[N - 1][:h, h:], -1j * np.eye(h))
+    assert np.array_equal(g[N - 1][h:, :h], 1j * np.eye(h))
+    z_top = np.diag([(-1.0) ** ((b >> (L - 1)) & 1) for b in range(h)])
+    assert np.array_equal(g[N - 2][:h, h:], z_top)
+    assert np.array_equal(g[N - 2][h:, :h], z_top)
+
+
+def test_pauli_table_matches_matrices():
+    """sigma_a sigma_b = i^p sigma_c from the table equals the 2x2 matrix product, and the
+    matrices are the textbook ones (sigma_x sigma_y = i sigma_z)."""
+    S = pauli.SIGMA
+    assert np.array_equal(S[1] @ S[2], 1j * S[3])
+    for a in range(4):
+        for b in range(4):
+            (c,), p = pauli.multiply(((a,), 0), ((b,), 0))
+            assert np.array_equal(S[a] @ S[b], (1j ** p) * S[c])
+
+
+def test_canonical_readoff_matches_dense():
+    """canonical(s) = (x, z, w) means s|m> = i^w (-1)^{popc(m & z)} |m ^ x> for every m."""
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        n = int(rng.integers(1, 6))
+        s = (tuple(int(a) for a in rng.integers(0, 4, n)), int(rng.integers(0, 4)))
+        M = pauli.dense(s)
+        x, z, w = pauli.canonical(s)
+        for m in range(1 << n):
+            col = np.zeros(1 << n, dtype=np.complex128)
+            col[m ^ x] = (1j ** w) * (-1) ** bin(m & z).count("1")
+            assert np.allclose(M[:, m], col)
+
+
+def test_hand_derived_terms_N8():
+    """Hand-derived block forms (tests/golden/hand_terms_N8.txt) from Eq. (S1)."""
+    rows = []
+    with open(os.path.join(GOLDEN, "hand_terms_N8.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    assert len(rows) == 3
+    for r in rows:
+        sub = tuple(int(v) for v in r[:4])
+        x, z, pU, pD = int(r[4], 2), int(r[5], 2), int(r[6]), int(r[7])
+        (lu, qu), (ld, qd) = pauli.term_blocks(8, sub)
+        assert pauli.canonical((lu, qu)) == (x, z, pU)
+        assert pauli.canonical((ld, qd)) == (x, z, pD)
+        # and the dense blocks of the full product agree
+        g = dense.gammas(8)
+        P = g[sub[0]] @ g[sub[1]] @ g[sub[2]] @ g[sub[3]]
+        assert np.array_equal(P[:8, :8], pauli.dense((lu, qu)))
+        assert np.array_equal(P[8:, 8:], pauli.dense((ld, qd)))
+
+
+@pytest.mark.parametrize("N", [8, 10, 12])
+def test_term_blocks_equal_dense_blocks(N):
+    """term_blocks (qubit-by-qubit products) equals the dense blocks of gamma_i gamma_j gamma_k gamma_l,
+    and the phase is real iff popcount(x & z) is even (Hermitian terms)."""
+    g = dense.gammas(N)
+    h = g[0].shape[0] // 2
+    rng = np.random.default_rng(N)
+    for _ in range(30):
+        sub = tuple(sorted(rng.choice(N, 4, replace=False).tolist()))
+        P = g[sub[0]] @ g[sub[1]] @ g[sub[2]] @ g[sub[3]]
+        (lu, pu), (ld, pd) = pauli.term_blocks(N, sub)
+        assert np.array_equal(P[:h, :h], pauli.dense((lu, pu)))
+        assert np.array_equal(P[h:, h:], pauli.dense((ld, pd)))
+        x, z, w = pauli.canonical((lu, pu))
+        assert (w % 2 == 0) == (bin(x & z).count("1") % 2 == 0)
+
+
+# --------------------------------------------------------------------------- ensemble
+def test_unrank_is_a_bijection():
+    N = 11
+    seen = set()
+    for idx in range(math.comb(N, 4)):
+        s = ensemble.unrank_colex4(idx)
+        assert 0 <= s[0] < s[1] < s[2] < s[3] < N
+        seen.add(s)
+    assert len(seen) == math.comb(N, 4)
+
+
+def test_sample_terms_structure():
+    subs, J, sigma = ensemble.sample_terms(16, 4, 1)
+    assert len(subs) == 64 and len(set(subs)) == 64
+    assert subs == sorted(subs)
+    assert all(0 <= s[0] < s[1] < s[2] < s[3] < 16 for s in subs)
+    # sigma^2 = 3!/(p N^3), p = K/C(N,4); dense limit p = 1 gives 6/N^3
+    assert abs(ensemble.coupling_sigma(10, math.comb(10, 4)) ** 2 - 6.0 / 1000) < 1e-18
+    assert abs(sigma ** 2 - 6.0 / ((64 / math.comb(16, 4)) * 16 ** 3)) < 1e-15
+    assert ensemble.n_terms(56, 4) == 224 and ensemble.n_terms(48, 4) == 192
+    assert ensemble.n_terms(56, 1.0 / 56) == 1
+
+
+def test_subsets_uniform():
+    """K=1 draws over many seeds are uniform over the C(8,4) = 70 subsets (chi-square)."""
+    counts = {}
+    n = 7000
+    for seed in range(n):
+        (s,), _, _ = ensemble.sample_terms(8, 1.0 / 8, seed)
+        counts[s] = counts.get(s, 0) + 1
+    assert len(counts) == 70
+    exp = n / 70
+    chi2 = sum((c - exp) ** 2 / exp for c in counts.values())
+    assert chi2 < 69 + 5 * math.sqrt(2 * 69)          # mean 69, sd ~11.7
+
+
+def test_coupling_law_moments():
+    """J ~ N(0, sigma^2): mean, variance and kurtosis over many draws."""
+    J = []
+    for seed in range(200):
+        _, Js, sigma = ensemble.sample_terms(12, 4, 1000 + seed)   # K = 48, sigma fixed
+        J.extend(Js)
+    J = np.array(J) / sigma
+    n = len(J)
+    assert abs(J.mean()) < 4 / math.sqrt(n)
+    assert abs(J.var() - 1) < 5 * math.sqrt(2 / n)
+    assert abs(np.mean(J ** 4) - 3) < 5 * math.sqrt(96 / n)
+
+
+def test_splitmix_finaliser_is_bijective():
+    """The finaliser inverts with the modular inverses of its multipliers."""
+    M = splitmix.MASK64
+
+    def unxorshift(y, s):
+        x = y
+        for _ in range(64 // s + 1):
+            x = y ^ (x >> s)
+        return x
+
+    inv1 = pow(splitmix._M1, -1, 1 << 64)
+    inv2 = pow(splitmix._M2, -1, 1 << 64)
+    rng = np.random.default_rng(3)
+    for v in rng.integers(0, 2 ** 63, 50, dtype=np.int64):
+        z0 = int(v) * 2 + 1
+        y = splitmix.mix(z0)
+        y = unxorshift(y, 31)
+        y = (y * inv2) & M
+        y = unxorshift(y, 27)
+        y = (y * inv1) & M
+        y = unxorshift(y, 30)
+        assert y == z0
+    # the stream is mix(seed + n GAMMA) and the vectorised finaliser agrees
+    g = splitmix.SplitMix64(12345)
+    outs = [g.next() for _ in range(5)]
+    assert outs == [splitmix.mix(12345 + (n + 1) * splitmix.GAMMA) for n in range(5)]
+    arr = splitmix.mix_array(np.array([(12345 + (n + 1) * splitmix.GAMMA) & M for n in range(5)], dtype=np.uint64))
+    assert [int(a) for a in arr] == outs
+
+
+def test_splitmix_bits_balanced():
+    g = splitmix.SplitMix64(99)
+    ones = np.zeros(64)
+    n = 20000
+    for _ in range(n):
+        r = g.next()
+        ones += [(r >> b) & 1 for b in range(64)]
+    assert np.all(np.abs(ones / n - 0.5) < 5 * 0.5 / math.sqrt(n))
+
+
+# --------------------------------------------------------------------------- Hamiltonian
+@pytest.mark.parametrize("N,k,seed", [(10, 3, 1), (12, 2, 2), (16, 4, 1)])
+def test_hamiltonian_invariants(N, k, seed):
+    """H Hermitian, Tr H = 0, Tr H^2/dim = sum J^2 / 16, [H, Gamma] = 0, Gamma ~ prod gamma."""
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    H = dense.hamiltonian(N, subs, J)
+    d = H.shape[0]
+    assert np.abs(H - H.conj().T).max() < 1e-15
+    assert abs(np.trace(H)) < 1e-13
+    assert abs(np.trace(H @ H).real / d - sum(x * x for x in J) / 16) < 1e-14
+    Gm = dense.parity_operator(N)
+    assert np.abs(H @ Gm - Gm @ H).max() < 1e-15
+    g = dense.gammas(N)
+    P = np.eye(d, dtype=np.complex128)
+    for gn in g:
+        P = P @ gn
+    ratio = P[0, 0] / Gm[0, 0]
+    assert abs(abs(ratio) - 1) < 1e-14 and np.allclose(P, ratio * Gm)
+
+
+def test_hamiltonian_two_terms_by_hand():
+    """H for two hand-picked terms equals the explicit sum of chi products."""
+    ch = dense.chis(8)
+    H = dense.hamiltonian(8, [(0, 1, 2, 3), (1, 2, 5, 7)], [0.5, -1.25])
+    ref = 0.5 * ch[0] @ ch[1] @ ch[2] @ ch[3] - 1.25 * ch[1] @ ch[2] @ ch[5] @ ch[7]
+    assert np.abs(H - ref).max() < 1e-16
+    # (0,1,2,3) is -Z1 on each block (hand fixture) and chi^4 carries 1/4
+    assert np.allclose(dense.hamiltonian(8, [(0, 1, 2, 3)], [1.0])[:8, :8],
+                       -0.25 * pauli.dense(((0, 3, 0), 0)))
+
+
+@pytest.mark.parametrize("N", [10, 12, 14, 16])
+def test_bott_periodicity_spectra(N):
+    """Parity-block spectra by N mod 8 (the Bott periodicity invoked in the main text):
+    N = 2, 6 mod 8: spec H_UU = spec H_DD; N = 4 mod 8: every level doubly degenerate
+    within each block; N = 0 mod 8: no pairing and no degeneracy."""
+    subs, J, _ = ensemble.sample_terms(N, 3, 5)
+    HU, HD = dense.blocks(dense.hamiltonian(N, subs, J))
+    eU = np.linalg.eigvalsh(HU)
+    eD = np.linalg.eigvalsh(HD)
+    r = N % 8
+    tol = 1e-12
+    if r in (2, 6):
+        assert np.abs(eU - eD).max() < tol
+    elif r == 4:
+        assert np.abs(eU[0::2] - eU[1::2]).max() < tol
+        assert np.abs(eD[0::2] - eD[1::2]).max() < tol
+    else:
+        assert np.abs(eU - eD).max() > 1e-3
+        assert np.min(np.diff(eU)) > 1e-10
+
+
+def test_parity_blocks_are_the_only_nonzero_blocks():
+    subs, J, _ = ensemble.sample_terms(12, 3, 3)
+    H = dense.hamiltonian(12, subs, J)
+    h = H.shape[0] // 2
+    assert np.abs(H[:h, h:]).max() == 0 and np.abs(H[h:, :h]).max() == 0
+
+
+# --------------------------------------------------------------------------- expm
+def test_expm_matches_scipy():
+    subs, J, _ = ensemble.sample_terms(12, 3, 4)
+    H = dense.hamiltonian(12, subs, J)
+    eg = dense.Eig(H)
+    v = np.random.default_rng(1).standard_normal(H.shape[0]) + 0j
+    for z in (-0.7j, 0.3 - 2.5j, -1.25, 2j - 0.5):
+        ref = scipy.linalg.expm(z * H) @ v
+        assert np.abs(eg.expm_apply(z, v) - ref).max() < 1e-12 * max(1, np.abs(ref).max())
+    # unitarity and composition
+    u = eg.expm_apply(-3.0j, v)
+    assert abs(np.linalg.norm(u) - np.linalg.norm(v)) < 1e-12
+    a = eg.expm_apply(0.4 - 1j, eg.expm_apply(-0.1 + 2j, v))
+    assert np.abs(a - eg.expm_apply(0.3 + 1j, v)).max() < 1e-12
+
+
+# --------------------------------------------------------------------------- OTOC
+def test_otoc_t0_beta0_is_minus_quarter():
+    """chi_i chi_j chi_i chi_j = -1/4 for i != j: F(0) = -1/4 at beta = 0 for any psi."""
+    N = 12
+    subs, J, _ = ensemble.sample_terms(N, 3, 9)
+    H = dense.hamiltonian(N, subs, J)
+    ch = dense.chis(N)
+    for (i, j) in ((1, 2), (N - 1, N - 2), (0, 7)):
+        assert abs(dense.otoc_trace(H, ch[i], ch[j], 0.0, [0.0])[0] + 0.25) < 1e-14
+        psi = haar.haar_state(N, 77, i)
+        assert abs(dense.otoc_state(H, ch[i], ch[j], 0.0, [0.0], psi)[0] + 0.25) < 1e-14
+
+
+@pytest.mark.parametrize("beta", [0.0, 5.0])
+def test_otoc_single_term_closed_forms(beta):
+    """H = J chi_a chi_b chi_c chi_d = (J/4) P with P^2 = 1.  chi_n anticommutes with P iff n
+    is in the term, which gives: both i, j in the term -> Re F = -cos(Jt)/4 for every psi
+    and every beta; exactly one in the term -> F = -1/4; neither -> t-independent."""
+    N = 12
+    Jv = 0.7
+    term = (1, 2, 5, 11)
+    H = dense.hamiltonian(N, [term], [Jv])
+    ch = dense.chis(N)
+    ts = np.linspace(0, 6, 13)
+    psi = haar.haar_state(N, 5, 0)
+    Fs = dense.otoc_state(H, ch[1], ch[2], beta, ts, psi)
+    Ft = dense.otoc_trace(H, ch[1], ch[2], beta, ts)
+    assert np.abs(Fs.real + np.cos(Jv * ts) / 4).max() < 1e-13
+    assert np.abs(Ft + np.cos(Jv * ts) / 4).max() < 1e-13
+    Fs = dense.otoc_state(H, ch[11], ch[3], beta, ts, psi)
+    assert np.abs(Fs + 0.25).max() < 1e-13
+    Fs = dense.otoc_state(H, ch[0], ch[3], beta, ts, psi)
+    assert np.abs(Fs - Fs[0]).max() < 1e-13
+
+
+def test_otoc_trace_is_real_and_state_average_converges():
+    """The trace is real (it equals its own conjugate by cyclicity) and the random-state
+    estimator averages to it (typicality, supplement Sec. I)."""
+    N = 10
+    subs, J, _ = ensemble.sample_terms(N, 3, 11)
+    H = dense.hamiltonian(N, subs, J)
+    ch = dense.chis(N)
+    ts = [0.0, 0.8, 2.0]
+    Ft = dense.otoc_trace(H, ch[N - 1], ch[N - 2], 2.0, ts)
+    assert np.abs(Ft.imag).max() < 1e-15
+    Fs = np.mean([dense.otoc_state(H, ch[N - 1], ch[N - 2], 2.0, ts, haar.haar_state(N, 3, v))
+                  for v in range(400)], axis=0)
+    # spread of one estimate ~ |F| / sqrt(dim); 400 vectors -> ~ 0.25/sqrt(32*400)
+    assert np.abs(Fs - Ft).max() < 0.02
+
+
+def test_otoc_equals_sum_of_parity_block_chains():
+    """The supplement's block form: <psi|O|psi> = <psi_U|O_UU|psi_U> + <psi_D|O_DD|psi_D>, where
+    every Majorana maps U <-> D.  Computed with dense blocks and compared with the full space."""
+    N = 12
+    subs, J, _ = ensemble.sample_terms(N, 3, 13)
+    H = dense.hamiltonian(N, subs, J)
+    ch = dense.chis(N)
+    h = H.shape[0] // 2
+    HU, HD = dense.blocks(H)
+    eU, eD = dense.Eig(HU), dense.Eig(HD)
+    i, j, beta, t = 3, 8, 4.0, 1.3
+    W, V = ch[i], ch[j]
+    psi = haar.haar_state(N, 21, 0)
+    full = dense.otoc_state(H, W, V, beta, [t], psi)[0]
+    tot = 0
+    for (eA, eB, WAB, VBA, ps) in (
+            (eU, eD, W[:h, h:], V[h:, :h], psi[:h]),
+            (eD, eU, W[h:, :h], V[:h, h:], psi[h:])):
+        r = eA.expm_apply(-beta / 8, ps)
+        r = VBA @ r
+        r = eB.expm_apply(-(1j * t + beta / 4), r)
+        r = WAB @ r
+        r = eA.expm_apply(1j * t - beta / 4, r)
+        r = VBA @ r
+        r = eB.expm_apply(-(1j * t + beta / 4), r)
+        r = WAB @ r
+        r = eA.expm_apply(1j * t - beta / 8, r)
+        tot += np.vdot(ps, r)
+    assert abs(tot - full) < 1e-13
+
+
+def test_normalise_curves():
+    F = np.array([[-0.25 + 0.1j, -0.2], [-0.25 - 0.1j, -0.1]])
+    raw, nrm, im = dense.normalise_curves(F)
+    assert np.allclose(raw, [-0.25, -0.15]) and np.allclose(nrm, [1.0, 0.6]) and np.allclose(im, [0, 0])
+
+
+# --------------------------------------------------------------------------- Green function
+def test_green_function_single_term():
+    """G(t) with gamma = gamma_n in the single term: gamma e^{-iHt} = e^{iHt} gamma, so
+    G(t) = <psi|e^{(2it - beta) H}|psi> and Re G at beta = 0 is cos(Jt/2)."""
+    N = 10
+    Jv = 0.9
+    H = dense.hamiltonian(N, [(0, 4, 6, 9)], [Jv])
+    g = dense.gammas(N)
+    psi = haar.haar_state(N, 8, 0)
+    ts = np.linspace(0, 5, 11)
+    G = dense.green_state(H, g[9], 0.0, ts, psi)
+    assert np.abs(G.real - np.cos(Jv * ts / 2)).max() < 1e-13
+    G0 = dense.green_state(H, g[9], 3.0, [0.0], psi)[0]
+    assert abs(G0 - np.vdot(psi, dense.Eig(H).expm_apply(-3.0, psi))) < 1e-13
+
+
+# --------------------------------------------------------------------------- Haar states
+def test_haar_state_properties():
+    N = 16
+    psi = haar.haar_state(N, 1001, 0)
+    d = 1 << (N // 2)
+    assert abs(np.vdot(psi, psi).real - 1) < 1e-14
+    raw = haar.raw_amplitudes(1001, 0, np.arange(d, dtype=np.uint64))
+    assert np.allclose(psi, raw / np.linalg.norm(raw))
+    assert abs(haar.raw_norm2(N, 1001, 0, chunk=64) - np.sum(np.abs(raw) ** 2)) < 1e-9
+    # independent vectors are nearly orthogonal; amplitudes are standard complex normals
+    psi2 = haar.haar_state(N, 1001, 1)
+    assert abs(np.vdot(psi, psi2)) < 5 / math.sqrt(d)
+    big = haar.raw_amplitudes(5, 3, np.arange(1 << 18, dtype=np.uint64))
+    n = big.size
+    assert abs(big.real.mean()) < 5 / math.sqrt(n) and abs(big.imag.mean()) < 5 / math.sqrt(n)
+    assert abs(big.real.var() - 1) < 5 * math.sqrt(2 / n) and abs(big.imag.var() - 1) < 5 * math.sqrt(2 / n)
+    assert abs(np.mean(big.real * big.imag)) < 5 / math.sqrt(n)
+
+
+# --------------------------------------------------------------------------- matrix-free rows
+@pytest.mark.parametrize("N,blk", [(12, 0), (12, 1), (16, 0), (16, 1)])
+def test_matfree_rows_match_dense(N, blk):
+    subs, J, _ = ensemble.sample_terms(N, 4, 17)
+    H = dense.hamiltonian(N, subs, J)
+    Hb = dense.blocks(H)[blk]
+    h = Hb.shape[0]
+    x = np.random.default_rng(2).standard_normal(h) + 1j * np.random.default_rng(3).standard_normal(h)
+    y = matfree.apply_rows(matfree.block_terms(N, subs, J, blk), lambda idx: x[idx.astype(np.int64)],
+                           np.arange(h, dtype=np.uint64))
+    assert np.abs(y - Hb @ x).max() < 1e-14
+
+
+def test_matfree_hermitian_at_large_N():
+    """<e_m, H e_n> = conj <e_n, H e_m> for sampled pairs at N = 48 (rows of unit vectors)."""
+    N = 48
+    subs, J, _ = ensemble.sample_terms(N, 4, 48)
+    terms = matfree.block_terms(N, subs, J, 0)
+    rng = np.random.default_rng(0)
+    h = 1 << (N // 2 - 1)
+    for _ in range(20):
+        m = int(rng.integers(0, h))
+        # H e_n has row m nonzero only for n = m ^ x_a: probe each such n
+        for labels, _c in terms[:10]:
+            n = m
+            for q, lab in enumerate(labels):
+                if lab in (pauli.X, pauli.Y):
+                    n ^= 1 << q
+            e = lambda idx, k=n: (idx == k).astype(np.complex128)
+            hmn = matfree.apply_rows(terms, e, np.array([m], dtype=np.uint64))[0]
+            f = lambda idx, k=m: (idx == k).astype(np.complex128)
+            hnm = matfree.apply_rows(terms, f, np.array([n], dtype=np.uint64))[0]
+            assert abs(hmn - np.conj(hnm)) < 1e-15
