@@ -1,0 +1,209 @@
+/*
+ * syk.h -- C ABI of libsyk: the sparse q=4 SYK Hamiltonian applied matrix-free to
+ * parity-block state vectors on an AMD Instinct MI355X (gfx950), and the Lanczos
+ * propagators and regularised OTOC built on it.
+ *
+ * Paper: A. M. Garcia-Garcia, C. Liu, J. J. M. Verbaarschot, "Sparsity independent
+ * Lyapunov exponent in the Sachdev-Ye-Kitaev model" (arXiv:2311.00639).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - N Majoranas, N even, 6 <= N <= 64.  L = N/2 - 1 block qubits; a parity block holds
+ *    2^L amplitudes; the full space 2^(L+1), the parity qubit being the most significant
+ *    index bit, U = parity 0 (first half), D = parity 1 (second half).
+ *  - Majoranas chi_n = gamma_n / sqrt(2) with gamma_n the Jordan-Wigner Pauli strings of
+ *    supplement Eq. (S1) (compact form): block strings A_0 = prod_q X_q and, for
+ *    1 <= n <= N-2, A_n = (Y if n odd else Z)_{floor((n-1)/2)} prod_{q >= floor((n+1)/2)} X_q;
+ *    gamma_n = X_parity (x) A_n (n <= N-2), gamma_{N-1} = Y_parity (x) 1, with
+ *    sigma_y = [[0,-i],[i,0]].  Qubit q is bit q of the amplitude index.
+ *  - H = sum_a J_a chi_i chi_j chi_k chi_l (Eq. (1)); each term restricted to a block is
+ *    (J_a/4) i^p X^x Z^z, Z applied first (the <bits, coeff> encoding of supplement Sec. I.A).
+ *  - State vectors are interleaved complex: (re, im) pairs of float (SYK_C64) or double
+ *    (SYK_C128).  Vector pointers are DEVICE pointers on the current HIP device unless a
+ *    parameter says "host"; the caller owns them.  Reductions (norms, dots, Lanczos
+ *    alpha/beta, the tridiagonal exponential) are done in double for both dtypes.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is enqueued on
+ *    it; functions returning host results synchronise it.
+ *  - Errors: every function returns a syk_status; no C++ exception crosses the ABI.  On
+ *    failure, syk_last_error() returns a thread-local message.  Output buffers are left
+ *    unspecified on failure.
+ */
+#ifndef SYK_H
+#define SYK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct syk_ham syk_ham;      /* opaque, owned by the library, immutable after create */
+
+typedef enum {
+    SYK_OK = 0,
+    SYK_EINVAL = 1,        /* invalid argument (range, null pointer, size mismatch) */
+    SYK_EUNSUPPORTED = 2,  /* valid but not supported (q != 4) */
+    SYK_ENOMEM = 3,        /* device or host allocation failed */
+    SYK_EDEVICE = 4,       /* a HIP runtime call failed, or no GPU */
+    SYK_ENOTCONV = 5,      /* Krylov step control could not meet the tolerance */
+    SYK_ENUMERIC = 6,      /* NaN/Inf met in a reduction */
+    SYK_ECANCELLED = 7     /* request cancelled (engine) */
+} syk_status;
+
+typedef enum { SYK_C64 = 0, SYK_C128 = 1 } syk_dtype;
+typedef enum { SYK_BLOCK_U = 0, SYK_BLOCK_D = 1 } syk_block;
+
+typedef struct {
+    int N, L, K;           /* Majoranas, block qubits, number of terms */
+    double k;              /* requested sparsity k (K = round(k N)) */
+    double p;              /* K / C(N,4) */
+    double sigma;          /* coupling standard deviation sqrt(3! / (p N^3)) */
+    double sum_J2;         /* sum_a J_a^2 (Tr H^2 / dim = sum_J2 / 16) */
+    uint64_t seed;
+    uint64_t block_dim;    /* 2^L */
+} syk_ham_info;
+
+/* ---------------------------------------------------------------- Hamiltonian
+ * Draw one disorder realisation of Eq. (1) (main text, "Sparse SYK Model"): exactly
+ * K = round(k N) distinct 4-subsets chosen uniformly and J ~ N(0, sigma^2),
+ * sigma^2 = 3!/(p N^3), p = K / C(N,4).  Draws come from one SplitMix64 stream seeded
+ * with `seed`: subset ranks by rejection (r >= 2^64 - 2^64 mod C(N,4) rejected), r mod
+ * C(N,4) unranked in the colex combinatorial number system, duplicates skipped, subsets
+ * sorted lexicographically, then per subset J = sigma sqrt(-2 ln u1) cos(2 pi u2) with
+ * u1 = ((r1>>11)+1) 2^-53, u2 = (r2>>11) 2^-53.  Host-only: needs no GPU; device term
+ * tables are uploaded lazily on first use on each device.
+ * Errors: EINVAL (N odd or outside [6,64], K < 1 or K > C(N,4), out == NULL),
+ * EUNSUPPORTED (q != 4), ENOMEM. */
+syk_status syk_create_hamiltonian(int N, int q, double k, uint64_t seed, syk_ham **out);
+
+/* Free a handle and its device tables on every device.  NULL is a no-op. */
+syk_status syk_destroy_hamiltonian(syk_ham *h);
+
+syk_status syk_ham_get_info(const syk_ham *h, syk_ham_info *out);
+
+/* Copy the term table to host arrays of capacity `cap` (>= K; any pointer may be NULL):
+ * ijkl[4a..4a+3] the sorted subset, J[a], and the block forms (J/4) i^phase X^x Z^z of
+ * gamma_i gamma_j gamma_k gamma_l on U (phase_U) and D (phase_D), phase in {0,1,2,3}.
+ * The product of the four strings is formed in canonical form by
+ * (X^a Z^b)(X^c Z^d) = (-1)^{popcount(b & c)} X^{a^c} Z^{b^d} (supplement Sec. I.A: product
+ * of spin operators = XOR of bits and a sign).  Host-only.  Errors: EINVAL (cap < K). */
+syk_status syk_get_terms(const syk_ham *h, size_t cap, int32_t *ijkl, double *J,
+                         uint64_t *xmask, uint64_t *zmask, int8_t *phase_U, int8_t *phase_D);
+
+/* ---------------------------------------------------------------- apply_H
+ * y = H_blk x, matrix-free (supplement Sec. I.A, Algorithm 1): for every m < 2^L,
+ * y[m] = sum_a (J_a/4) i^{p_a} (-1)^{popcount((m ^ x_a) & z_a)} x[m ^ x_a].
+ * x, y: device, `nvec` vectors, vector v at element offset v*ld, n_amps = 2^L complex
+ * elements each, ld >= n_amps.  x and y must not overlap.  y is overwritten.
+ * Errors: EINVAL (n_amps != 2^L, nvec < 1, ld < n_amps, null), EDEVICE. */
+syk_status syk_apply_H(const syk_ham *h, syk_block blk, syk_dtype dt, const void *x, void *y,
+                       uint64_t n_amps, int nvec, uint64_t ld, void *stream);
+
+/* ---------------------------------------------------------------- Haar states
+ * Random state of the typicality estimator (supplement Sec. I: a Haar-random state is
+ * drawn and its parity components used).  Full-space amplitude n (n < 2^L: U block,
+ * else D block, index n - 2^L) is a standard complex Gaussian from two SplitMix64
+ * finaliser outputs of counters: base = mix(state_seed + (v+1) G),
+ * w1 = mix(base + (2n+1) G), w2 = mix(base + (2n+2) G), G = 0x9E3779B97F4A7C15,
+ * psi_n = sqrt(-2 ln u1) e^{2 pi i u2}; the vector is normalised in double over both
+ * blocks.  psi_U, psi_D: device, 2^L elements each.  Errors: EINVAL, EDEVICE. */
+syk_status syk_haar_state(int N, uint64_t state_seed, int v, syk_dtype dt,
+                          void *psi_U, void *psi_D, void *stream);
+
+/* ---------------------------------------------------------------- Majorana insertion
+ * y = scale * (gamma_n)_{dst,src} x, the block of gamma_n mapping block `src` to the other
+ * block (supplement Sec. I: Majoranas are block off-diagonal).  n <= N-2: the block is A_n
+ * in both directions; n = N-1: gamma_{N-1}^{UD} = -i (src = D), gamma_{N-1}^{DU} = +i
+ * (src = U).  scale = scale_re + i scale_im.  x, y device, 2^L elements; x == y allowed
+ * only for n = N-1 or when A_n flips no qubit.  Errors: EINVAL, EDEVICE. */
+syk_status syk_apply_majorana(int N, int n, syk_block src, syk_dtype dt, const void *x, void *y,
+                              uint64_t n_amps, double scale_re, double scale_im, void *stream);
+
+/* ---------------------------------------------------------------- Krylov propagator */
+typedef struct {
+    int m;             /* maximum Krylov dimension per sub-step, 2 <= m <= 128 */
+    double tol;        /* accepted a-posteriori error per propagation, relative to ||v|| */
+    int reorth;        /* 0: three-term recurrence only; 1: local (second pass against
+                          v_j, v_{j-1}); 2: full classical Gram-Schmidt */
+    int max_substeps;  /* 0 = unlimited */
+} syk_krylov_opts;
+
+typedef struct {
+    int substeps;      /* restarts taken */
+    int matvecs;       /* apply_H calls */
+    int breakdown;     /* 1 if an invariant subspace ended a Lanczos run (exact) */
+    double err_est;    /* sum over sub-steps of the accepted error estimates, relative */
+} syk_krylov_stats;
+
+/* Fill `o` with defaults for dtype dt (m = 30, tol = 1e-12 for C128 / 1e-7 for C64,
+ * reorth = 1, max_substeps = 0). */
+void syk_krylov_default_opts(syk_dtype dt, syk_krylov_opts *o);
+
+/* out = e^{z H_blk} v, z = z_re + i z_im, by Lanczos with restarts (the restarted Krylov
+ * time evolution of supplement Sec. I.A, here with step control): up to m Lanczos steps
+ * (alpha_j, beta_j reduced in double), the small exponential e^{tau z T_j} e_1 from the
+ * eigendecomposition of the real symmetric tridiagonal T_j in double, a-posteriori error
+ * estimate ||v|| beta_j |[e^{tau z T_j} e_1]_j|; a step ends early once the estimate
+ * meets the tolerance for the remaining tau, else the largest tau that meets it is taken
+ * and the propagation restarts from the result.  beta_j ~ 0 is an invariant subspace
+ * (exact result).  v, out: device, n_amps = 2^L; out == v allowed.  stats may be NULL.
+ * Uses a library-owned device workspace of (m + 2) vectors, reused across calls.
+ * Errors: EINVAL, ENOMEM, EDEVICE, ENOTCONV (max_substeps exceeded), ENUMERIC. */
+syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double z_re, double z_im,
+                           const void *v, void *out, uint64_t n_amps, const syk_krylov_opts *o,
+                           syk_krylov_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------- OTOC */
+typedef struct {
+    int nvec;              /* Haar vectors averaged (>= 1) */
+    uint64_t state_seed;   /* vector v uses syk_haar_state(N, state_seed, v, ...) */
+    syk_dtype dtype;       /* state-vector precision; reductions are double either way */
+    syk_krylov_opts krylov;
+    int profile;           /* 1: time every apply_H launch with HIP events on `stream` */
+} syk_otoc_opts;
+
+typedef struct {
+    long long matvecs;
+    long long substeps;
+    double seconds;        /* wall time of the call */
+    double max_err_est;    /* largest per-propagation relative error estimate */
+    double apply_ms;       /* profile = 1: summed event-timed duration of apply_H launches */
+    long long apply_launches;
+} syk_otoc_stats;
+
+/* Regularised OTOC of Eq. (2) with W = chi_i, V = chi_j (0-based; the paper uses
+ * i = N-1, j = N-2), by the supplement's random-state estimator
+ *   F_v(t) = <psi| e^{(it-b/8)H} W e^{-(it+b/4)H} V e^{(it-b/4)H} W e^{-(it+b/4)H} V e^{-bH/8} |psi>
+ * evaluated as the sum of its U-block and D-block chains ("+ swap UD").  t: host, nt
+ * non-decreasing times >= 0.  Outputs (host, nt doubles; any may be NULL):
+ * F_raw[n] = mean_v Re F_v(t_n), F_imag[n] = mean_v Im F_v(t_n),
+ * F_norm[n] = F_raw[n] / F_raw(t = 0) (t = 0 is evaluated if t[0] != 0).
+ * Synchronises `stream`.  Errors: EINVAL (i == j, out of range, nt < 1, t decreasing or
+ * negative, nvec < 1), ENOMEM, EDEVICE, ENOTCONV, ENUMERIC. */
+syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t, int nt,
+                    const syk_otoc_opts *o, double *F_raw, double *F_norm, double *F_imag,
+                    syk_otoc_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------- helpers */
+
+/* Device bytes the OTOC of one request needs (Krylov basis, chain vectors, scratch);
+ * the supplement's minimum is (v+3) vectors for a Krylov dimension v.  Errors: EINVAL. */
+syk_status syk_workspace_bytes(int N, int m, syk_dtype dt, int nvec, uint64_t *bytes);
+
+/* Host-only small exponential used by syk_krylov_expm: c = e^{z T} e_1 for the real
+ * symmetric tridiagonal T (diagonal alpha[0..n-1], off-diagonal beta[0..n-2]);
+ * c_re, c_im: host, n doubles.  Errors: EINVAL (n < 1 or > 1024, null), ENUMERIC. */
+syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, double z_re, double z_im,
+                            double *c_re, double *c_im);
+
+/* Release the library's cached device workspaces on the current device. */
+syk_status syk_release_workspace(void);
+
+const char *syk_status_string(syk_status s);
+const char *syk_last_error(void);    /* thread-local; "" if none */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYK_H */

@@ -1,0 +1,29 @@
+"""Python binding of libsyk (argument marshalling only).
+
+Every step of the path runs in the HIP library ``libsyk.so`` built from ``csrc/``;
+this module only converts arguments (torch tensors are passed by device pointer,
+streams by their HIP handle) and raises on non-OK status codes.  There is no
+Python or CPU fallback: if the library is missing, importing the binding raises.
+
+Names follow the C ABI in ``include/syk.h``: create_hamiltonian, apply_H,
+haar_state, apply_majorana, krylov_expm, otoc, workspace_bytes, tridiag_expm.
+"""
+from ._lib import (  # noqa: F401
+    C64,
+    C128,
+    BLOCK_U,
+    BLOCK_D,
+    SykError,
+    Hamiltonian,
+    KrylovOpts,
+    apply_H,
+    apply_majorana,
+    create_hamiltonian,
+    haar_state,
+    krylov_expm,
+    library_path,
+    otoc,
+    release_workspace,
+    tridiag_expm,
+    workspace_bytes,
+)

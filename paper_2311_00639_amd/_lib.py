@@ -1,0 +1,255 @@
+"""ctypes declarations for libsyk and thin wrappers with the C ABI's names."""
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libsyk.so")
+
+C64, C128 = 0, 1
+BLOCK_U, BLOCK_D = 0, 1
+
+STATUS = {0: "SYK_OK", 1: "SYK_EINVAL", 2: "SYK_EUNSUPPORTED", 3: "SYK_ENOMEM", 4: "SYK_EDEVICE",
+          5: "SYK_ENOTCONV", 6: "SYK_ENUMERIC", 7: "SYK_ECANCELLED"}
+
+
+class SykError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(_LIBPATH):
+    raise ImportError(f"libsyk.so not built ({_LIBPATH}); run `python -m paper_2311_00639_amd.build`")
+_lib = ct.CDLL(_LIBPATH)
+
+
+def library_path() -> str:
+    return _LIBPATH
+
+
+class HamInfo(ct.Structure):
+    _fields_ = [("N", ct.c_int), ("L", ct.c_int), ("K", ct.c_int), ("k", ct.c_double), ("p", ct.c_double),
+                ("sigma", ct.c_double), ("sum_J2", ct.c_double), ("seed", ct.c_uint64), ("block_dim", ct.c_uint64)]
+
+
+class KrylovOpts(ct.Structure):
+    _fields_ = [("m", ct.c_int), ("tol", ct.c_double), ("reorth", ct.c_int), ("max_substeps", ct.c_int)]
+
+
+class KrylovStats(ct.Structure):
+    _fields_ = [("substeps", ct.c_int), ("matvecs", ct.c_int), ("breakdown", ct.c_int), ("err_est", ct.c_double)]
+
+
+class OtocOpts(ct.Structure):
+    _fields_ = [("nvec", ct.c_int), ("state_seed", ct.c_uint64), ("dtype", ct.c_int), ("krylov", KrylovOpts),
+                ("profile", ct.c_int)]
+
+
+class OtocStats(ct.Structure):
+    _fields_ = [("matvecs", ct.c_longlong), ("substeps", ct.c_longlong), ("seconds", ct.c_double),
+                ("max_err_est", ct.c_double), ("apply_ms", ct.c_double), ("apply_launches", ct.c_longlong)]
+
+
+_vp, _u64, _i, _d = ct.c_void_p, ct.c_uint64, ct.c_int, ct.c_double
+_dp = ct.POINTER(ct.c_double)
+_SIGS = {
+    "syk_create_hamiltonian": [_i, _i, _d, _u64, ct.POINTER(_vp)],
+    "syk_destroy_hamiltonian": [_vp],
+    "syk_ham_get_info": [_vp, ct.POINTER(HamInfo)],
+    "syk_get_terms": [_vp, ct.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp],
+    "syk_apply_H": [_vp, _i, _i, _vp, _vp, _u64, _i, _u64, _vp],
+    "syk_haar_state": [_i, _u64, _i, _i, _vp, _vp, _vp],
+    "syk_apply_majorana": [_i, _i, _i, _i, _vp, _vp, _u64, _d, _d, _vp],
+    "syk_krylov_expm": [_vp, _i, _i, _d, _d, _vp, _vp, _u64, ct.POINTER(KrylovOpts), ct.POINTER(KrylovStats), _vp],
+    "syk_otoc": [_vp, _i, _i, _d, _dp, _i, ct.POINTER(OtocOpts), _dp, _dp, _dp, ct.POINTER(OtocStats), _vp],
+    "syk_workspace_bytes": [_i, _i, _i, _i, ct.POINTER(_u64)],
+    "syk_tridiag_expm": [_i, _dp, _dp, _d, _d, _dp, _dp],
+    "syk_release_workspace": [],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ct.c_int
+_lib.syk_status_string.argtypes = [ct.c_int]
+_lib.syk_status_string.restype = ct.c_char_p
+_lib.syk_last_error.argtypes = []
+_lib.syk_last_error.restype = ct.c_char_p
+_lib.syk_krylov_default_opts.argtypes = [ct.c_int, ct.POINTER(KrylovOpts)]
+_lib.syk_krylov_default_opts.restype = None
+
+
+def _check(status):
+    if status != 0:
+        raise SykError(status, _lib.syk_last_error().decode())
+
+
+def _ptr(a):
+    """Device pointer of a torch tensor, or an int address."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    return a.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dtype_of(t):
+    import torch
+    if t.dtype == torch.complex64:
+        return C64
+    if t.dtype == torch.complex128:
+        return C128
+    raise TypeError("state vectors must be complex64 or complex128")
+
+
+class Hamiltonian:
+    """Owned handle to one disorder realisation (syk_create_hamiltonian)."""
+
+    def __init__(self, N: int, q: int, k: float, seed: int):
+        h = _vp()
+        _check(_lib.syk_create_hamiltonian(N, q, float(k), seed, ct.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = HamInfo()
+        _check(_lib.syk_ham_get_info(self._h, ct.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in HamInfo._fields_}
+
+    def terms(self) -> dict:
+        K = self.info()["K"]
+        ijkl = np.zeros((K, 4), dtype=np.int32)
+        J = np.zeros(K)
+        x = np.zeros(K, dtype=np.uint64)
+        z = np.zeros(K, dtype=np.uint64)
+        pu = np.zeros(K, dtype=np.int8)
+        pd = np.zeros(K, dtype=np.int8)
+        _check(_lib.syk_get_terms(self._h, K, ijkl.ctypes.data, J.ctypes.data, x.ctypes.data, z.ctypes.data,
+                                  pu.ctypes.data, pd.ctypes.data))
+        return {"ijkl": ijkl, "J": J, "xmask": x, "zmask": z, "phase_U": pu, "phase_D": pd}
+
+    def close(self):
+        if self._h:
+            _lib.syk_destroy_hamiltonian(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def create_hamiltonian(N: int, q: int, k: float, seed: int) -> Hamiltonian:
+    return Hamiltonian(N, q, k, seed)
+
+
+def apply_H(ham: Hamiltonian, block: int, x, y, nvec: int = 1, ld: int = None, stream=None):
+    """y = H_block x for torch tensors x, y of complex dtype on the GPU.
+
+    With nvec > 1 the tensors hold nvec vectors of leading dimension ld (elements)."""
+    n = 1 << ham.info()["L"]
+    ld = n if ld is None else ld
+    _check(_lib.syk_apply_H(ham.handle, block, _dtype_of(x), _ptr(x), _ptr(y), n, nvec, ld, _stream(stream)))
+
+
+def haar_state(N: int, state_seed: int, v: int, psi_U, psi_D, stream=None):
+    _check(_lib.syk_haar_state(N, state_seed, v, _dtype_of(psi_U), _ptr(psi_U), _ptr(psi_D), _stream(stream)))
+
+
+def apply_majorana(N: int, n: int, src_block: int, x, y, scale: complex = 1.0, stream=None):
+    amps = 1 << (N // 2 - 1)
+    sc = complex(scale)
+    _check(_lib.syk_apply_majorana(N, n, src_block, _dtype_of(x), _ptr(x), _ptr(y), amps, sc.real, sc.imag,
+                                   _stream(stream)))
+
+
+def default_krylov_opts(dtype: int) -> KrylovOpts:
+    o = KrylovOpts()
+    _lib.syk_krylov_default_opts(dtype, ct.byref(o))
+    return o
+
+
+def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None, tol: float = None,
+                reorth: int = None, max_substeps: int = None, stream=None) -> dict:
+    """out = e^{z H_block} v.  Returns the Krylov statistics as a dict."""
+    dt = _dtype_of(v)
+    o = default_krylov_opts(dt)
+    if m is not None:
+        o.m = m
+    if tol is not None:
+        o.tol = tol
+    if reorth is not None:
+        o.reorth = reorth
+    if max_substeps is not None:
+        o.max_substeps = max_substeps
+    st = KrylovStats()
+    z = complex(z)
+    n = 1 << ham.info()["L"]
+    _check(_lib.syk_krylov_expm(ham.handle, block, dt, z.real, z.imag, _ptr(v), _ptr(out), n, ct.byref(o),
+                                ct.byref(st), _stream(stream)))
+    return {f: getattr(st, f) for f, _ in KrylovStats._fields_}
+
+
+def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_seed: int = 0, dtype: int = C128,
+         m: int = None, tol: float = None, reorth: int = None, profile: bool = False, stream=None):
+    """Regularised OTOC (Eq. (2)) by the random-state estimator.  Returns
+    (F_raw, F_norm, F_imag, stats) with numpy float64 arrays."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    nt = t.size
+    o = OtocOpts()
+    o.nvec = nvec
+    o.state_seed = state_seed
+    o.dtype = dtype
+    o.krylov = default_krylov_opts(dtype)
+    o.profile = 1 if profile else 0
+    if m is not None:
+        o.krylov.m = m
+    if tol is not None:
+        o.krylov.tol = tol
+    if reorth is not None:
+        o.krylov.reorth = reorth
+    raw = np.zeros(nt)
+    nrm = np.zeros(nt)
+    im = np.zeros(nt)
+    st = OtocStats()
+    dp = lambda a: a.ctypes.data_as(_dp)
+    _check(_lib.syk_otoc(ham.handle, i, j, float(beta), dp(t), nt, ct.byref(o), dp(raw), dp(nrm), dp(im),
+                         ct.byref(st), _stream(stream)))
+    return raw, nrm, im, {f: getattr(st, f) for f, _ in OtocStats._fields_}
+
+
+def workspace_bytes(N: int, m: int, dtype: int, nvec: int = 1) -> int:
+    b = ct.c_uint64()
+    _check(_lib.syk_workspace_bytes(N, m, dtype, nvec, ct.byref(b)))
+    return b.value
+
+
+def tridiag_expm(alpha, beta, z: complex) -> np.ndarray:
+    """e^{z T} e_1 for the symmetric tridiagonal T (host computation in the library)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    n = a.size
+    cr = np.zeros(n)
+    ci = np.zeros(n)
+    z = complex(z)
+    dp = lambda v: v.ctypes.data_as(_dp)
+    _check(_lib.syk_tridiag_expm(n, dp(a), dp(b) if b.size else None, z.real, z.imag, dp(cr), dp(ci)))
+    return cr + 1j * ci
+
+
+def release_workspace():
+    _check(_lib.syk_release_workspace())

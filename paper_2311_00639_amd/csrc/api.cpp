@@ -1,0 +1,334 @@
+// extern "C" entry points of libsyk: argument checks, error translation, dispatch.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+
+#include "krylov.hpp"
+#include "otoc.hpp"
+
+struct syk_ham {
+    syk::Hamiltonian h;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+syk_status guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return SYK_OK;
+    } catch (const syk::Error &e) {
+        g_last_error = e.msg;
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return SYK_ENOMEM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return SYK_EDEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return SYK_EDEVICE;
+    }
+}
+
+void require(bool c, const char *msg) {
+    if (!c) syk::fail(SYK_EINVAL, msg);
+}
+
+void check_device() {
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n < 1) syk::fail(SYK_EDEVICE, "no HIP device available");
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+uint64_t block_amps(int N) { return 1ULL << (N / 2 - 1); }
+
+void check_N(int N) { require(N % 2 == 0 && N >= 6 && N <= 64, "N must be even with 6 <= N <= 64"); }
+
+void check_opts(const syk_krylov_opts &o) {
+    require(o.m >= 2 && o.m <= 128, "Krylov m must lie in [2, 128]");
+    require(o.tol > 0.0 && std::isfinite(o.tol), "Krylov tol must be positive");
+    require(o.reorth >= 0 && o.reorth <= 2, "reorth must be 0, 1 or 2");
+    require(o.max_substeps >= 0, "max_substeps must be >= 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+syk_status syk_create_hamiltonian(int N, int q, double k, uint64_t seed, syk_ham **out) {
+    return guarded([&] {
+        require(out != nullptr, "out is NULL");
+        *out = nullptr;
+        check_N(N);
+        if (q != 4) syk::fail(SYK_EUNSUPPORTED, "only q = 4 is defined (Eq. (1))");
+        require(std::isfinite(k) && k > 0.0, "k must be positive");
+        auto *h = new syk_ham();
+        try {
+            syk::build_hamiltonian(h->h, N, k, seed);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+syk_status syk_destroy_hamiltonian(syk_ham *h) {
+    return guarded([&] { delete h; });
+}
+
+syk_status syk_ham_get_info(const syk_ham *h, syk_ham_info *out) {
+    return guarded([&] {
+        require(h && out, "NULL argument");
+        const auto &H = h->h;
+        out->N = H.N;
+        out->L = H.L;
+        out->K = H.K;
+        out->k = H.k;
+        out->p = H.p;
+        out->sigma = H.sigma;
+        out->sum_J2 = H.sum_J2;
+        out->seed = H.seed;
+        out->block_dim = 1ULL << H.L;
+    });
+}
+
+syk_status syk_get_terms(const syk_ham *h, size_t cap, int32_t *ijkl, double *J, uint64_t *xmask, uint64_t *zmask,
+                         int8_t *phase_U, int8_t *phase_D) {
+    return guarded([&] {
+        require(h != nullptr, "NULL handle");
+        const auto &H = h->h;
+        require(cap >= static_cast<size_t>(H.K), "cap is smaller than the number of terms");
+        const size_t K = static_cast<size_t>(H.K);
+        if (ijkl) std::memcpy(ijkl, H.ijkl.data(), 4 * K * sizeof(int32_t));
+        if (J) std::memcpy(J, H.J.data(), K * sizeof(double));
+        if (xmask) std::memcpy(xmask, H.xmask.data(), K * sizeof(uint64_t));
+        if (zmask) std::memcpy(zmask, H.zmask.data(), K * sizeof(uint64_t));
+        if (phase_U) std::memcpy(phase_U, H.phase[0].data(), K);
+        if (phase_D) std::memcpy(phase_D, H.phase[1].data(), K);
+    });
+}
+
+syk_status syk_apply_H(const syk_ham *h, syk_block blk, syk_dtype dt, const void *x, void *y, uint64_t n_amps,
+                       int nvec, uint64_t ld, void *stream) {
+    return guarded([&] {
+        require(h && x && y, "NULL argument");
+        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        require(n_amps == block_amps(h->h.N), "n_amps must equal 2^(N/2-1)");
+        require(nvec >= 1 && nvec <= 65535, "nvec must lie in [1, 65535]");
+        require(ld >= n_amps, "ld must be >= n_amps");
+        check_device();
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        const auto &tb = H.tables(blk);
+        if (dt == SYK_C64)
+            syk::launch_apply_h<float>(tb, static_cast<const float *>(x), static_cast<float *>(y),
+                                       static_cast<uint32_t>(n_amps), nvec, ld, as_stream(stream));
+        else
+            syk::launch_apply_h<double>(tb, static_cast<const double *>(x), static_cast<double *>(y),
+                                        static_cast<uint32_t>(n_amps), nvec, ld, as_stream(stream));
+    });
+}
+
+syk_status syk_haar_state(int N, uint64_t state_seed, int v, syk_dtype dt, void *psi_U, void *psi_D, void *stream) {
+    return guarded([&] {
+        check_N(N);
+        require(psi_U && psi_D && psi_U != psi_D, "psi_U, psi_D must be distinct non-NULL buffers");
+        require(v >= 0, "v must be >= 0");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        check_device();
+        const uint64_t n = block_amps(N);
+        const int np = syk::reduction_blocks(n);
+        auto &ws = syk::thread_workspace(1);
+        ws.ensure(static_cast<size_t>(np + 1) * sizeof(double));
+        double *part = reinterpret_cast<double *>(ws.ptr());
+        double *sum = part + np;
+        hipStream_t s = as_stream(stream);
+        if (dt == SYK_C64) {
+            syk::launch_haar_raw<float>(state_seed, v, N / 2 - 1, static_cast<float *>(psi_U),
+                                        static_cast<float *>(psi_D), part, np, s);
+            syk::launch_reduce_partials(part, np, 1, sum, s);
+            syk::launch_scale_pair<float>(static_cast<float *>(psi_U), static_cast<float *>(psi_D), n, sum, s);
+        } else {
+            syk::launch_haar_raw<double>(state_seed, v, N / 2 - 1, static_cast<double *>(psi_U),
+                                         static_cast<double *>(psi_D), part, np, s);
+            syk::launch_reduce_partials(part, np, 1, sum, s);
+            syk::launch_scale_pair<double>(static_cast<double *>(psi_U), static_cast<double *>(psi_D), n, sum, s);
+        }
+        // the workspace is reused by later calls on this thread: keep it alive until done
+        SYK_HIP(hipStreamSynchronize(s));
+    });
+}
+
+syk_status syk_apply_majorana(int N, int n, syk_block src, syk_dtype dt, const void *x, void *y, uint64_t n_amps,
+                              double scale_re, double scale_im, void *stream) {
+    return guarded([&] {
+        check_N(N);
+        require(n >= 0 && n < N, "Majorana index out of range");
+        require(src == SYK_BLOCK_U || src == SYK_BLOCK_D, "invalid block");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        require(x && y, "NULL argument");
+        require(n_amps == block_amps(N), "n_amps must equal 2^(N/2-1)");
+        uint32_t bx = 0, bz = 0;
+        int bw = 0;
+        if (n < N - 1) syk::block_majorana(N, n, bx, bz, bw);
+        require(x != y || bx == 0, "in-place Majorana insertion needs a string without flips");
+        check_device();
+        std::complex<double> sc(scale_re, scale_im);
+        if (n == N - 1) sc *= std::complex<double>(0.0, src == SYK_BLOCK_U ? 1.0 : -1.0);
+        hipStream_t s = as_stream(stream);
+        if (dt == SYK_C64)
+            syk::launch_majorana<float>(bx, bz, bw, sc.real(), sc.imag(), static_cast<const float *>(x),
+                                        static_cast<float *>(y), n_amps, s);
+        else
+            syk::launch_majorana<double>(bx, bz, bw, sc.real(), sc.imag(), static_cast<const double *>(x),
+                                         static_cast<double *>(y), n_amps, s);
+    });
+}
+
+void syk_krylov_default_opts(syk_dtype dt, syk_krylov_opts *o) {
+    if (!o) return;
+    o->m = 30;
+    o->tol = (dt == SYK_C64) ? 1e-7 : 1e-12;
+    o->reorth = 1;
+    o->max_substeps = 0;
+}
+
+syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double z_re, double z_im, const void *v,
+                           void *out, uint64_t n_amps, const syk_krylov_opts *o, syk_krylov_stats *stats,
+                           void *stream) {
+    return guarded([&] {
+        require(h && v && out && o, "NULL argument");
+        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        require(n_amps == block_amps(h->h.N), "n_amps must equal 2^(N/2-1)");
+        require(std::isfinite(z_re) && std::isfinite(z_im), "z must be finite");
+        check_opts(*o);
+        check_device();
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        const auto &tb = H.tables(blk);
+        syk_krylov_stats st{};
+        auto &ws = syk::thread_workspace(0);
+        hipStream_t s = as_stream(stream);
+        const std::complex<double> z(z_re, z_im);
+        if (dt == SYK_C64) {
+            ws.ensure(syk::krylov_workspace_bytes(n_amps, o->m, sizeof(float)));
+            syk::KrylovRun<float> kr(tb, n_amps, o->m, ws.ptr(), s);
+            kr.run(z, static_cast<const float *>(v), static_cast<float *>(out), *o, st);
+        } else {
+            ws.ensure(syk::krylov_workspace_bytes(n_amps, o->m, sizeof(double)));
+            syk::KrylovRun<double> kr(tb, n_amps, o->m, ws.ptr(), s);
+            kr.run(z, static_cast<const double *>(v), static_cast<double *>(out), *o, st);
+        }
+        SYK_HIP(hipStreamSynchronize(s));
+        if (stats) *stats = st;
+    });
+}
+
+syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t, int nt, const syk_otoc_opts *o,
+                    double *F_raw, double *F_norm, double *F_imag, syk_otoc_stats *stats, void *stream) {
+    return guarded([&] {
+        require(h && t && o, "NULL argument");
+        const int N = h->h.N;
+        require(i >= 0 && i < N && j >= 0 && j < N && i != j, "Majorana indices must be distinct and in [0, N)");
+        require(nt >= 1, "nt must be >= 1");
+        require(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
+        require(o->nvec >= 1, "nvec must be >= 1");
+        require(o->dtype == SYK_C64 || o->dtype == SYK_C128, "invalid dtype");
+        check_opts(o->krylov);
+        for (int k = 0; k < nt; ++k) {
+            require(std::isfinite(t[k]) && t[k] >= 0.0, "t must be finite and >= 0");
+            if (k) require(t[k] >= t[k - 1], "t must be non-decreasing");
+        }
+        check_device();
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<double> ts(t, t + nt);
+        const bool prepend = ts[0] != 0.0;
+        if (prepend) ts.insert(ts.begin(), 0.0);
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        const uint64_t n = 1ULL << H.L;
+        syk_otoc_stats st{};
+        std::vector<std::complex<double>> F;
+        auto &ws = syk::thread_workspace(0);
+        hipStream_t s = as_stream(stream);
+        if (o->dtype == SYK_C64) {
+            ws.ensure(syk::otoc_workspace_bytes(n, o->krylov.m, sizeof(float)));
+            syk::otoc_run<float>(H, i, j, beta, ts, *o, F, st, ws.ptr(), s);
+        } else {
+            ws.ensure(syk::otoc_workspace_bytes(n, o->krylov.m, sizeof(double)));
+            syk::otoc_run<double>(H, i, j, beta, ts, *o, F, st, ws.ptr(), s);
+        }
+        const double f0 = F[0].real();
+        const int off = prepend ? 1 : 0;
+        for (int k = 0; k < nt; ++k) {
+            const std::complex<double> f = F[k + off];
+            if (F_raw) F_raw[k] = f.real();
+            if (F_imag) F_imag[k] = f.imag();
+            if (F_norm) F_norm[k] = f.real() / f0;
+        }
+        st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats) *stats = st;
+    });
+}
+
+syk_status syk_workspace_bytes(int N, int m, syk_dtype dt, int nvec, uint64_t *bytes) {
+    return guarded([&] {
+        check_N(N);
+        require(m >= 2 && m <= 128, "m must lie in [2, 128]");
+        require(nvec >= 1, "nvec must be >= 1");
+        require(bytes != nullptr, "bytes is NULL");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        const size_t e = (dt == SYK_C64) ? sizeof(float) : sizeof(double);
+        *bytes = syk::otoc_workspace_bytes(block_amps(N), m, e);
+    });
+}
+
+syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, double z_re, double z_im, double *c_re,
+                            double *c_im) {
+    return guarded([&] {
+        require(n >= 1 && n <= 1024, "n must lie in [1, 1024]");
+        require(alpha && c_re && c_im && (n == 1 || beta), "NULL argument");
+        syk::TriExp te(n, alpha, beta);
+        if (!te.ok()) syk::fail(SYK_ENUMERIC, "tridiagonal eigensolver failed");
+        std::vector<std::complex<double>> c(n);
+        te.apply(std::complex<double>(z_re, z_im), c.data());
+        for (int i = 0; i < n; ++i) {
+            c_re[i] = c[i].real();
+            c_im[i] = c[i].imag();
+        }
+    });
+}
+
+syk_status syk_release_workspace(void) {
+    return guarded([&] {
+        check_device();
+        syk::thread_workspace(0).release();
+        syk::thread_workspace(1).release();
+    });
+}
+
+const char *syk_status_string(syk_status s) {
+    switch (s) {
+        case SYK_OK: return "SYK_OK";
+        case SYK_EINVAL: return "SYK_EINVAL";
+        case SYK_EUNSUPPORTED: return "SYK_EUNSUPPORTED";
+        case SYK_ENOMEM: return "SYK_ENOMEM";
+        case SYK_EDEVICE: return "SYK_EDEVICE";
+        case SYK_ENOTCONV: return "SYK_ENOTCONV";
+        case SYK_ENUMERIC: return "SYK_ENUMERIC";
+        case SYK_ECANCELLED: return "SYK_ECANCELLED";
+    }
+    return "SYK_UNKNOWN";
+}
+
+const char *syk_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,454 @@
+// HIP kernels of libsyk for gfx950: matrix-free apply_H (supplement Algorithm 1), Haar
+// states, Majorana insertions, and the vector kernels of the Lanczos propagator.
+//
+// Complex vectors are interleaved (re, im) of float or double, addressed as float2 /
+// double2.  Every reduction accumulates in double and writes one partial per workgroup;
+// partials are combined in a fixed order by reduce_partials, so results are repeatable.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace syk {
+
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+template <typename T> using V2 = typename Vec2<T>::type;
+
+constexpr int kBlock = 256;
+
+static inline int grid_for(uint64_t n, int per_thread = 1) {
+    uint64_t g = (n + static_cast<uint64_t>(kBlock) * per_thread - 1) / (static_cast<uint64_t>(kBlock) * per_thread);
+    if (g < 1) g = 1;
+    if (g > 65535ULL * 16) g = 65535ULL * 16;
+    return static_cast<int>(g);
+}
+
+int reduction_blocks(uint64_t n) {
+    uint64_t g = n / (kBlock * 8);
+    if (g < 1) g = 1;
+    if (g > 2048) g = 2048;
+    return static_cast<int>(g);
+}
+
+// block-wide sum of W doubles per thread into out[0..W) (thread 0 writes)
+template <int W>
+__device__ inline void block_sum(double (&v)[W], double *out) {
+    __shared__ double sh[W][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        double s = v[k];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) sh[k][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += sh[k][w];
+            out[k] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ apply_H
+// One output amplitude per thread and loop over all terms: the partner x[m ^ x_a] is
+// gathered straight from global memory, the sign is the parity of m & z_a (the parity of
+// x_a & z_a is folded into c_a), real-phase terms first, then i-phase terms.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) apply_h_gather(const uint32_t *__restrict__ tx,
+                                                         const uint32_t *__restrict__ tz,
+                                                         const T *__restrict__ tc, int n_real, int K,
+                                                         const V2<T> *__restrict__ x, V2<T> *__restrict__ y,
+                                                         uint32_t n_amps, uint64_t ld) {
+    const uint64_t vo = static_cast<uint64_t>(blockIdx.y) * ld;
+    x += vo;
+    y += vo;
+    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < n_amps; m += gridDim.x * kBlock) {
+        T ar = 0, ai = 0;
+        for (int a = 0; a < n_real; ++a) {
+            const V2<T> v = x[m ^ tx[a]];
+            const T c = (__popc(m & tz[a]) & 1) ? -tc[a] : tc[a];
+            ar += c * v.x;
+            ai += c * v.y;
+        }
+        for (int a = n_real; a < K; ++a) {
+            const V2<T> v = x[m ^ tx[a]];
+            const T c = (__popc(m & tz[a]) & 1) ? -tc[a] : tc[a];
+            ar -= c * v.y;
+            ai += c * v.x;
+        }
+        y[m] = V2<T>{ar, ai};
+    }
+}
+
+template <typename T> static const T *coef_ptr(const DeviceTables &tb);
+template <> const float *coef_ptr<float>(const DeviceTables &tb) { return tb.c32; }
+template <> const double *coef_ptr<double>(const DeviceTables &tb) { return tb.c64; }
+
+template <typename T>
+void launch_apply_h(const DeviceTables &tb, const T *x, T *y, uint32_t n_amps, int nvec, uint64_t ld,
+                    hipStream_t s) {
+    dim3 grid(grid_for(n_amps), nvec);
+    hipLaunchKernelGGL(apply_h_gather<T>, grid, dim3(kBlock), 0, s, tb.x, tb.z, coef_ptr<T>(tb), tb.n_real, tb.K,
+                       reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
+    SYK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Haar states
+__device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ inline double2 haar_amp(uint64_t base, uint64_t n) {
+    const uint64_t G = 0x9E3779B97F4A7C15ULL;
+    const uint64_t w1 = mix64(base + (2 * n + 1) * G);
+    const uint64_t w2 = mix64(base + (2 * n + 2) * G);
+    const double u1 = static_cast<double>((w1 >> 11) + 1) * 0x1p-53;
+    const double u2 = static_cast<double>(w2 >> 11) * 0x1p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(2.0 * M_PI * u2, &sn, &cs);
+    return double2{r * cs, r * sn};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) haar_raw(uint64_t base, int L, V2<T> *__restrict__ pu,
+                                                   V2<T> *__restrict__ pd, double *__restrict__ partials) {
+    const uint64_t h = 1ULL << L;
+    double acc[1] = {0.0};
+    for (uint64_t b = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; b < h;
+         b += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        const double2 a = haar_amp(base, b);
+        const double2 d = haar_amp(base, h + b);
+        acc[0] += a.x * a.x + a.y * a.y + d.x * d.x + d.y * d.y;
+        pu[b] = V2<T>{static_cast<T>(a.x), static_cast<T>(a.y)};
+        pd[b] = V2<T>{static_cast<T>(d.x), static_cast<T>(d.y)};
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
+template <typename T>
+void launch_haar_raw(uint64_t state_seed, int v, int L, T *psi_U, T *psi_D, double *partials, int n_part,
+                     hipStream_t s) {
+    const uint64_t base = splitmix_mix(state_seed + static_cast<uint64_t>(v + 1) * 0x9E3779B97F4A7C15ULL);
+    hipLaunchKernelGGL(haar_raw<T>, dim3(n_part), dim3(kBlock), 0, s, base, L, reinterpret_cast<V2<T> *>(psi_U),
+                       reinterpret_cast<V2<T> *>(psi_D), partials);
+    SYK_HIP(hipGetLastError());
+}
+
+// a, b *= 1/sqrt(norm2[0]) -- the normalisation of a full-space state split in two blocks.
+// For double the raw amplitudes are rescaled as stored; for float the stored rounded raw
+// values are rescaled (a relative change of at most one float ulp from normalising first).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) scale_pair(V2<T> *__restrict__ a, V2<T> *__restrict__ b, uint64_t n,
+                                                     const double *__restrict__ norm2) {
+    const double inv = 1.0 / sqrt(norm2[0]);
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = a[i], w = b[i];
+        a[i] = V2<T>{static_cast<T>(u.x * inv), static_cast<T>(u.y * inv)};
+        b[i] = V2<T>{static_cast<T>(w.x * inv), static_cast<T>(w.y * inv)};
+    }
+}
+
+template <typename T>
+void launch_scale_pair(T *a, T *b, uint64_t n, const double *norm2_dev, hipStream_t s) {
+    hipLaunchKernelGGL(scale_pair<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(a),
+                       reinterpret_cast<V2<T> *>(b), n, norm2_dev);
+    SYK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Majorana insertion
+// dst[m] = s * (-1)^{popc((m ^ x) & z)} * src[m ^ x],  s complex (phase i^w folded in).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) majorana_kernel(uint32_t x, uint32_t z, double sre, double sim,
+                                                          const V2<T> *__restrict__ src, V2<T> *__restrict__ dst,
+                                                          uint64_t n) {
+    for (uint64_t m = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; m < n;
+         m += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        const uint32_t k = static_cast<uint32_t>(m) ^ x;
+        const V2<T> v = src[k];
+        const double sg = (__popc(k & z) & 1) ? -1.0 : 1.0;
+        const double vr = sg * static_cast<double>(v.x), vi = sg * static_cast<double>(v.y);
+        dst[m] = V2<T>{static_cast<T>(sre * vr - sim * vi), static_cast<T>(sre * vi + sim * vr)};
+    }
+}
+
+template <typename T>
+void launch_majorana(uint32_t x, uint32_t z, int w, double sre, double sim, const T *src, T *dst, uint64_t n,
+                     hipStream_t s) {
+    // fold i^w into the scale
+    for (int k = 0; k < (w & 3); ++k) {
+        const double r = -sim, i = sre;
+        sre = r;
+        sim = i;
+    }
+    hipLaunchKernelGGL(majorana_kernel<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, x, z, sre, sim,
+                       reinterpret_cast<const V2<T> *>(src), reinterpret_cast<V2<T> *>(dst), n);
+    SYK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ reductions
+template <typename T>
+__global__ void __launch_bounds__(kBlock) dot_partials(const V2<T> *__restrict__ a, const V2<T> *__restrict__ b,
+                                                       uint64_t n, double *__restrict__ partials) {
+    double acc[2] = {0.0, 0.0};
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        const V2<T> u = a[i], v = b[i];
+        acc[0] += static_cast<double>(u.x) * v.x + static_cast<double>(u.y) * v.y;
+        acc[1] += static_cast<double>(u.x) * v.y - static_cast<double>(u.y) * v.x;
+    }
+    block_sum<2>(acc, partials + 2 * blockIdx.x);
+}
+
+template <typename T>
+void launch_dot_partials(const T *a, const T *b, uint64_t n, double *partials, int n_part, hipStream_t s) {
+    hipLaunchKernelGGL(dot_partials<T>, dim3(n_part), dim3(kBlock), 0, s, reinterpret_cast<const V2<T> *>(a),
+                       reinterpret_cast<const V2<T> *>(b), n, partials);
+    SYK_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) norm2_partials(const V2<T> *__restrict__ a, uint64_t n,
+                                                         double *__restrict__ partials) {
+    double acc[1] = {0.0};
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        const V2<T> u = a[i];
+        acc[0] += static_cast<double>(u.x) * u.x + static_cast<double>(u.y) * u.y;
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
+template <typename T>
+void launch_norm2_partials(const T *a, uint64_t n, double *partials, int n_part, hipStream_t s) {
+    hipLaunchKernelGGL(norm2_partials<T>, dim3(n_part), dim3(kBlock), 0, s, reinterpret_cast<const V2<T> *>(a), n,
+                       partials);
+    SYK_HIP(hipGetLastError());
+}
+
+// dst[k] = sum_p partials[p * width + k], fixed order; width <= 2 * 130
+__global__ void __launch_bounds__(kBlock) reduce_partials_kernel(const double *__restrict__ partials, int n_part,
+                                                                 int width, double *__restrict__ dst) {
+    for (int k = 0; k < width; ++k) {
+        double acc[1] = {0.0};
+        for (int p = threadIdx.x; p < n_part; p += kBlock) acc[0] += partials[static_cast<size_t>(p) * width + k];
+        block_sum<1>(acc, dst + k);
+        __syncthreads();
+    }
+}
+
+void launch_reduce_partials(const double *partials, int n_part, int width, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kBlock), 0, s, partials, n_part, width, dst);
+    SYK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ Lanczos vector kernels
+// w -= beta_prev * vprev (vprev may be null, beta_prev = sqrt(beta2_prev[0])); partial <vcur, w>
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lanczos_orth1(V2<T> *__restrict__ w, const V2<T> *__restrict__ vprev,
+                                                        const V2<T> *__restrict__ vcur,
+                                                        const double *__restrict__ beta2_prev, uint64_t n,
+                                                        double *__restrict__ partials) {
+    const T bp = vprev ? static_cast<T>(sqrt(beta2_prev[0])) : T(0);
+    double acc[2] = {0.0, 0.0};
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = w[i];
+        if (vprev) {
+            const V2<T> p = vprev[i];
+            u.x -= bp * p.x;
+            u.y -= bp * p.y;
+            w[i] = u;
+        }
+        const V2<T> c = vcur[i];
+        acc[0] += static_cast<double>(c.x) * u.x + static_cast<double>(c.y) * u.y;
+        acc[1] += static_cast<double>(c.x) * u.y - static_cast<double>(c.y) * u.x;
+    }
+    block_sum<2>(acc, partials + 2 * blockIdx.x);
+}
+
+template <typename T>
+void launch_lanczos_orth1(T *w, const T *vprev, const T *vcur, const double *beta_prev, uint64_t n,
+                          double *partials, int n_part, hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_orth1<T>, dim3(n_part), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
+                       reinterpret_cast<const V2<T> *>(vprev), reinterpret_cast<const V2<T> *>(vcur), beta_prev,
+                       n, partials);
+    SYK_HIP(hipGetLastError());
+}
+
+// w -= alpha_re * vcur; partial ||w||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lanczos_orth2(V2<T> *__restrict__ w, const V2<T> *__restrict__ vcur,
+                                                        const double *__restrict__ alpha, uint64_t n,
+                                                        double *__restrict__ partials) {
+    const T al = static_cast<T>(alpha[0]);
+    double acc[1] = {0.0};
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = w[i];
+        const V2<T> c = vcur[i];
+        u.x -= al * c.x;
+        u.y -= al * c.y;
+        w[i] = u;
+        acc[0] += static_cast<double>(u.x) * u.x + static_cast<double>(u.y) * u.y;
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
+template <typename T>
+void launch_lanczos_orth2(T *w, const T *vcur, const double *alpha, uint64_t n, double *partials, int n_part,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_orth2<T>, dim3(n_part), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
+                       reinterpret_cast<const V2<T> *>(vcur), alpha, n, partials);
+    SYK_HIP(hipGetLastError());
+}
+
+// w *= 1/beta where beta = sqrt(norm2[0]); w = 0 if beta underflows (invariant subspace)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lanczos_normalize(V2<T> *__restrict__ w, const double *__restrict__ norm2,
+                                                            uint64_t n) {
+    const double b = sqrt(norm2[0]);
+    const T inv = (b > 1e-300) ? static_cast<T>(1.0 / b) : T(0);
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = w[i];
+        u.x *= inv;
+        u.y *= inv;
+        w[i] = u;
+    }
+}
+
+template <typename T>
+void launch_lanczos_normalize(T *w, const double *norm2, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_normalize<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
+                       norm2, n);
+    SYK_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) scale_copy(const V2<T> *__restrict__ src, V2<T> *__restrict__ dst,
+                                                     uint64_t n, double scale) {
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        const V2<T> u = src[i];
+        dst[i] = V2<T>{static_cast<T>(u.x * scale), static_cast<T>(u.y * scale)};
+    }
+}
+
+template <typename T>
+void launch_scale_copy(const T *src, T *dst, uint64_t n, double scale, hipStream_t s) {
+    hipLaunchKernelGGL(scale_copy<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, reinterpret_cast<const V2<T> *>(src),
+                       reinterpret_cast<V2<T> *>(dst), n, scale);
+    SYK_HIP(hipGetLastError());
+}
+
+// out[i] = sum_k coef[k] basis[k][i], coef complex double (re, im interleaved)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) combine_kernel(const V2<T> *__restrict__ basis, uint64_t stride, int nb,
+                                                         const double *__restrict__ coef, V2<T> *__restrict__ out,
+                                                         uint64_t n) {
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        double ar = 0.0, ai = 0.0;
+        for (int k = 0; k < nb; ++k) {
+            const V2<T> v = basis[k * stride + i];
+            const double cr = coef[2 * k], ci = coef[2 * k + 1];
+            ar += cr * v.x - ci * v.y;
+            ai += cr * v.y + ci * v.x;
+        }
+        out[i] = V2<T>{static_cast<T>(ar), static_cast<T>(ai)};
+    }
+}
+
+template <typename T>
+void launch_combine(const T *basis, uint64_t stride, int nb, const double *coef_dev, T *out, uint64_t n,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_for(n, 2)), dim3(kBlock), 0, s,
+                       reinterpret_cast<const V2<T> *>(basis), stride, nb, coef_dev,
+                       reinterpret_cast<V2<T> *>(out), n);
+    SYK_HIP(hipGetLastError());
+}
+
+// partials[p][k] = sum_i conj(v_k[i]) w[i] for k < nb (complex, width 2 nb)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) multi_dot_kernel(const V2<T> *__restrict__ basis, uint64_t stride, int nb,
+                                                           const V2<T> *__restrict__ w, uint64_t n,
+                                                           double *__restrict__ partials) {
+    for (int k = 0; k < nb; ++k) {
+        double acc[2] = {0.0, 0.0};
+        const V2<T> *v = basis + k * stride;
+        for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+             i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+            const V2<T> a = v[i], b = w[i];
+            acc[0] += static_cast<double>(a.x) * b.x + static_cast<double>(a.y) * b.y;
+            acc[1] += static_cast<double>(a.x) * b.y - static_cast<double>(a.y) * b.x;
+        }
+        block_sum<2>(acc, partials + (static_cast<size_t>(blockIdx.x) * nb + k) * 2);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+void launch_multi_dot_partials(const T *basis, uint64_t stride, int nb, const T *w, uint64_t n, double *partials,
+                               int n_part, hipStream_t s) {
+    hipLaunchKernelGGL(multi_dot_kernel<T>, dim3(n_part), dim3(kBlock), 0, s, reinterpret_cast<const V2<T> *>(basis),
+                       stride, nb, reinterpret_cast<const V2<T> *>(w), n, partials);
+    SYK_HIP(hipGetLastError());
+}
+
+// w -= sum_k c_k v_k (c complex double); partial ||w||^2 of the result
+template <typename T>
+__global__ void __launch_bounds__(kBlock) subtract_proj_kernel(V2<T> *__restrict__ w, const V2<T> *__restrict__ basis,
+                                                               uint64_t stride, int nb,
+                                                               const double *__restrict__ coef, uint64_t n) {
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = w[i];
+        double ar = u.x, ai = u.y;
+        for (int k = 0; k < nb; ++k) {
+            const V2<T> v = basis[k * stride + i];
+            const double cr = coef[2 * k], ci = coef[2 * k + 1];
+            ar -= cr * v.x - ci * v.y;
+            ai -= cr * v.y + ci * v.x;
+        }
+        w[i] = V2<T>{static_cast<T>(ar), static_cast<T>(ai)};
+    }
+}
+
+template <typename T>
+void launch_subtract_proj(T *w, const T *basis, uint64_t stride, int nb, const double *coef_dev, uint64_t n,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(subtract_proj_kernel<T>, dim3(grid_for(n, 2)), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
+                       reinterpret_cast<const V2<T> *>(basis), stride, nb, coef_dev, n);
+    SYK_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ instantiations
+#define SYK_INST(T)                                                                                                \
+    template void launch_apply_h<T>(const DeviceTables &, const T *, T *, uint32_t, int, uint64_t, hipStream_t);   \
+    template void launch_haar_raw<T>(uint64_t, int, int, T *, T *, double *, int, hipStream_t);                    \
+    template void launch_scale_pair<T>(T *, T *, uint64_t, const double *, hipStream_t);                           \
+    template void launch_majorana<T>(uint32_t, uint32_t, int, double, double, const T *, T *, uint64_t,            \
+                                     hipStream_t);                                                                 \
+    template void launch_dot_partials<T>(const T *, const T *, uint64_t, double *, int, hipStream_t);              \
+    template void launch_norm2_partials<T>(const T *, uint64_t, double *, int, hipStream_t);                       \
+    template void launch_lanczos_orth1<T>(T *, const T *, const T *, const double *, uint64_t, double *, int,      \
+                                          hipStream_t);                                                            \
+    template void launch_lanczos_orth2<T>(T *, const T *, const double *, uint64_t, double *, int, hipStream_t);   \
+    template void launch_lanczos_normalize<T>(T *, const double *, uint64_t, hipStream_t);                         \
+    template void launch_scale_copy<T>(const T *, T *, uint64_t, double, hipStream_t);                             \
+    template void launch_combine<T>(const T *, uint64_t, int, const double *, T *, uint64_t, hipStream_t);         \
+    template void launch_subtract_proj<T>(T *, const T *, uint64_t, int, const double *, uint64_t, hipStream_t);   \
+    template void launch_multi_dot_partials<T>(const T *, uint64_t, int, const T *, uint64_t, double *, int,       \
+                                               hipStream_t);
+SYK_INST(float)
+SYK_INST(double)
+
+}  // namespace syk

@@ -1,0 +1,293 @@
+// Lanczos propagator out = e^{z H_blk} v (the restarted Krylov time evolution of
+// supplement Sec. I.A), with a-posteriori step control.
+//
+// One sub-step: Lanczos on the normalised start vector builds V_k and the real symmetric
+// tridiagonal T_k (alpha_j = Re <v_j, H v_j - beta_{j-1} v_{j-1}>, beta_j = ||w_j||, both
+// reduced in double on the device).  The small exponential c(tau) = e^{tau z T_k} e_1 comes
+// from the eigendecomposition of T_k (implicit QL, double).  The estimate
+// err(tau) = beta_k |c_{k-1}(tau)| bounds the error of ||v|| V_k c(tau) relative to ||v||
+// (Saad 1992).  A sub-step of fraction tau of z is accepted when err(tau) <= tol * tau,
+// so accepted errors sum to at most tol.  beta_k ~ 0 means V_k spans an invariant
+// subspace and the result is exact.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+
+#include "krylov.hpp"
+
+namespace syk {
+
+// ------------------------------------------------------------------ tridiagonal eigensolver
+// Implicit QL iteration with shifts for a real symmetric tridiagonal matrix (Bowdler,
+// Martin, Reinsch & Wilkinson, Numer. Math. 11 (1968)): d <- eigenvalues, Z <- orthonormal
+// eigenvectors (column k of Z, row-major n x n).  e[i] couples d[i] and d[i+1].
+bool tridiag_eig(int n, std::vector<double> &d, std::vector<double> e, std::vector<double> &Z) {
+    Z.assign(static_cast<size_t>(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) Z[static_cast<size_t>(i) * n + i] = 1.0;
+    e.resize(n, 0.0);
+    e[n - 1] = 0.0;
+    const double eps = 2.220446049250313e-16;
+    for (int l = 0; l < n; ++l) {
+        int iter = 0;
+        for (;;) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= eps * dd) break;
+            }
+            if (m == l) break;
+            if (++iter > 200) return false;
+            // shift: eigenvalue of the leading 2x2 block closest to d[l]
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            int i = m - 1;
+            bool deflated = false;
+            for (; i >= l; --i) {
+                const double f = s * e[i];
+                const double b = c * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {          // underflow: split here and restart the sweep
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    deflated = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                for (int k = 0; k < n; ++k) {
+                    double *row = &Z[static_cast<size_t>(k) * n];
+                    const double zf = row[i + 1];
+                    row[i + 1] = s * row[i] + c * zf;
+                    row[i] = c * row[i] - s * zf;
+                }
+            }
+            if (deflated) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    return true;
+}
+
+TriExp::TriExp(int n, const double *alpha, const double *beta_off) : n_(n) {
+    lam_.assign(alpha, alpha + n);
+    std::vector<double> e(std::max(n, 1), 0.0);
+    for (int i = 0; i + 1 < n; ++i) e[i] = beta_off[i];
+    ok_ = tridiag_eig(n, lam_, e, Z_);
+    for (double v : lam_)
+        if (!std::isfinite(v)) ok_ = false;
+}
+
+// c = Z diag(e^{z lam}) Z^T e_1
+void TriExp::apply(std::complex<double> z, std::complex<double> *c) const {
+    std::vector<std::complex<double>> w(n_);
+    for (int k = 0; k < n_; ++k) w[k] = std::exp(z * lam_[k]) * Z_[k];          // Z[0][k] = Z_[k]
+    for (int i = 0; i < n_; ++i) {
+        std::complex<double> acc = 0.0;
+        const double *row = &Z_[static_cast<size_t>(i) * n_];
+        for (int k = 0; k < n_; ++k) acc += row[k] * w[k];
+        c[i] = acc;
+    }
+}
+
+std::complex<double> TriExp::last(std::complex<double> z) const {
+    std::complex<double> acc = 0.0;
+    const double *row = &Z_[static_cast<size_t>(n_ - 1) * n_];
+    for (int k = 0; k < n_; ++k) acc += row[k] * std::exp(z * lam_[k]) * Z_[k];
+    return acc;
+}
+
+// ------------------------------------------------------------------ apply_H timing
+ApplyTimer::~ApplyTimer() {
+    for (auto e : pool_) hipEventDestroy(e);
+}
+
+void ApplyTimer::begin(hipStream_t s) {
+    while (pool_.size() < used_ + 2) {
+        hipEvent_t e;
+        SYK_HIP(hipEventCreate(&e));
+        pool_.push_back(e);
+    }
+    SYK_HIP(hipEventRecord(pool_[used_], s));
+}
+
+void ApplyTimer::end(hipStream_t s) {
+    SYK_HIP(hipEventRecord(pool_[used_ + 1], s));
+    used_ += 2;
+}
+
+void ApplyTimer::flush() {
+    for (size_t k = 0; k + 1 < used_; k += 2) {
+        float t = 0.0f;
+        SYK_HIP(hipEventElapsedTime(&t, pool_[k], pool_[k + 1]));
+        ms += t;
+        launches += 1;
+    }
+    used_ = 0;
+}
+
+// ------------------------------------------------------------------ Lanczos driver
+size_t krylov_workspace_bytes(uint64_t n, int m, size_t elem_bytes) {
+    const size_t vec = static_cast<size_t>(n) * 2 * elem_bytes;
+    const size_t part = static_cast<size_t>(reduction_blocks(n)) * 2 * (m + 2) * sizeof(double);
+    const size_t scal = static_cast<size_t>(8 * (m + 4)) * sizeof(double);
+    auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+    return static_cast<size_t>(m + 1) * up(vec) + up(part) + up(scal);
+}
+
+template <typename T>
+KrylovRun<T>::KrylovRun(const DeviceTables &tb, uint64_t n, int m, char *ws, hipStream_t s)
+    : tb_(tb), n_(n), m_(m), s_(s) {
+    auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+    vec_stride_ = up(static_cast<size_t>(n) * 2 * sizeof(T)) / (2 * sizeof(T));
+    basis_ = reinterpret_cast<T *>(ws);
+    char *p = ws + static_cast<size_t>(m + 1) * vec_stride_ * 2 * sizeof(T);
+    n_part_ = reduction_blocks(n);
+    partials_ = reinterpret_cast<double *>(p);
+    p += up(static_cast<size_t>(n_part_) * 2 * (m + 2) * sizeof(double));
+    alpha_ = reinterpret_cast<double *>(p);   // 2 (m+1)
+    beta2_ = alpha_ + 2 * (m + 2);            // m+2
+    coef_ = beta2_ + (m + 2);                 // 2 (m+2)
+    scratch_ = coef_ + 2 * (m + 2);           // 2 (m+2)
+}
+
+template <typename T>
+double KrylovRun<T>::norm(const T *v) {
+    launch_norm2_partials<T>(v, n_, partials_, n_part_, s_);
+    launch_reduce_partials(partials_, n_part_, 1, scratch_, s_);
+    double h = 0.0;
+    SYK_HIP(hipMemcpyAsync(&h, scratch_, sizeof(double), hipMemcpyDeviceToHost, s_));
+    SYK_HIP(hipStreamSynchronize(s_));
+    if (timer_) timer_->flush();
+    if (!std::isfinite(h)) fail(SYK_ENUMERIC, "non-finite norm in Krylov propagation");
+    return std::sqrt(h);
+}
+
+// one Lanczos iteration j: fills slot j+1, alpha[j], beta2[j+1]
+template <typename T>
+void KrylovRun<T>::iterate(int j, int reorth) {
+    T *vj = vec(j);
+    T *w = vec(j + 1);
+    if (timer_) timer_->begin(s_);
+    launch_apply_h<T>(tb_, vj, w, static_cast<uint32_t>(n_), 1, n_, s_);
+    if (timer_) timer_->end(s_);
+    launch_lanczos_orth1<T>(w, j > 0 ? vec(j - 1) : nullptr, vj, beta2_ + j, n_, partials_, n_part_, s_);
+    launch_reduce_partials(partials_, n_part_, 2, alpha_ + 2 * j, s_);
+    launch_lanczos_orth2<T>(w, vj, alpha_ + 2 * j, n_, partials_, n_part_, s_);
+    if (reorth > 0) {
+        const int first = (reorth == 1) ? std::max(0, j - 1) : 0;
+        const int nb = j + 1 - first;
+        launch_multi_dot_partials<T>(vec(first), vec_stride_, nb, w, n_, partials_, n_part_, s_);
+        launch_reduce_partials(partials_, n_part_, 2 * nb, scratch_, s_);
+        launch_subtract_proj<T>(w, vec(first), vec_stride_, nb, scratch_, n_, s_);
+        launch_norm2_partials<T>(w, n_, partials_, n_part_, s_);
+    }
+    launch_reduce_partials(partials_, n_part_, 1, beta2_ + j + 1, s_);
+    launch_lanczos_normalize<T>(w, beta2_ + j + 1, n_, s_);
+}
+
+template <typename T>
+void KrylovRun<T>::run(std::complex<double> z, const T *v, T *out, const syk_krylov_opts &o, syk_krylov_stats &st) {
+    double nrm = norm(v);
+    if (nrm == 0.0 || z == std::complex<double>(0.0, 0.0)) {
+        if (out != v) launch_scale_copy<T>(v, out, n_, 1.0, s_);
+        return;
+    }
+    const bool every = n_ >= (1ULL << 20);        // large vectors: a host check per iteration is cheap
+    double remaining = 1.0;
+    const T *cur = v;
+    std::vector<double> ha(2 * (m_ + 2)), hb(m_ + 2);
+    std::vector<std::complex<double>> c(m_ + 1);
+    std::vector<double> coef(2 * (m_ + 1));
+    while (remaining > 0.0) {
+        if (o.max_substeps > 0 && st.substeps >= o.max_substeps)
+            fail(SYK_ENOTCONV, "Krylov propagation exceeded max_substeps");
+        launch_scale_copy<T>(cur, vec(0), n_, 1.0 / nrm, s_);
+        SYK_HIP(hipMemsetAsync(beta2_, 0, sizeof(double), s_));
+        int k = 0;                 // Lanczos vectors built
+        double tau = 0.0;
+        bool done = false;
+        int next_check = every ? 1 : 4;
+        for (int j = 0; j < m_ && !done; ++j) {
+            iterate(j, o.reorth);
+            k = j + 1;
+            st.matvecs += 1;
+            if (k < next_check && k < m_) continue;
+            next_check = every ? k + 1 : k + std::max(2, k / 4);
+            SYK_HIP(hipMemcpyAsync(ha.data(), alpha_, 2 * k * sizeof(double), hipMemcpyDeviceToHost, s_));
+            SYK_HIP(hipMemcpyAsync(hb.data(), beta2_, (k + 1) * sizeof(double), hipMemcpyDeviceToHost, s_));
+            SYK_HIP(hipStreamSynchronize(s_));
+            if (timer_) timer_->flush();
+            std::vector<double> al(k), bo(std::max(k - 1, 1));
+            double tnorm = 0.0;
+            for (int i = 0; i < k; ++i) {
+                al[i] = ha[2 * i];
+                if (!std::isfinite(al[i])) fail(SYK_ENUMERIC, "non-finite Lanczos alpha");
+                tnorm = std::max(tnorm, std::fabs(al[i]));
+            }
+            for (int i = 0; i + 1 < k; ++i) {
+                bo[i] = std::sqrt(hb[i + 1]);
+                tnorm = std::max(tnorm, bo[i]);
+            }
+            const double bk = std::sqrt(hb[k]);
+            if (!std::isfinite(bk)) fail(SYK_ENUMERIC, "non-finite Lanczos beta");
+            TriExp te(k, al.data(), bo.data());
+            if (!te.ok()) fail(SYK_ENUMERIC, "tridiagonal eigensolver failed");
+            const bool breakdown = bk <= 1e-14 * std::max(tnorm, 1e-300);
+            auto err = [&](double f) { return breakdown ? 0.0 : bk * std::abs(te.last(f * z)); };
+            if (err(remaining) <= o.tol * remaining) {
+                tau = remaining;
+                done = true;
+                if (breakdown) st.breakdown = 1;
+            } else if (k == m_) {
+                // largest fraction f <= remaining with err(f) <= tol f (bisection in log f)
+                double lo = 0.0, hi = remaining;
+                for (int it = 0; it < 200; ++it) {
+                    const double mid = (lo == 0.0) ? hi * 0.5 : std::sqrt(lo * hi);
+                    if (err(mid) <= o.tol * mid)
+                        lo = mid;
+                    else
+                        hi = mid;
+                    if (lo > 0.0 && hi / lo < 1.0 + 1e-3) break;
+                    if (lo == 0.0 && hi < 1e-14 * remaining) break;
+                }
+                if (lo <= 1e-12 * remaining) fail(SYK_ENOTCONV, "Krylov step size underflow (tolerance too strict)");
+                tau = lo;
+                done = true;
+            }
+            if (done) {
+                te.apply(tau * z, c.data());
+                st.err_est += err(tau);
+                for (int i = 0; i < k; ++i) {
+                    coef[2 * i] = nrm * c[i].real();
+                    coef[2 * i + 1] = nrm * c[i].imag();
+                }
+            }
+        }
+        // the combination writes `out`; the start vector already lives in the basis
+        SYK_HIP(hipMemcpyAsync(coef_, coef.data(), 2 * k * sizeof(double), hipMemcpyHostToDevice, s_));
+        launch_combine<T>(basis_, vec_stride_, k, coef_, out, n_, s_);
+        st.substeps += 1;
+        remaining -= tau;
+        if (remaining <= 1e-15) break;
+        cur = out;
+        nrm = norm(out);
+        if (nrm == 0.0) break;
+    }
+}
+
+template class KrylovRun<float>;
+template class KrylovRun<double>;
+
+}  // namespace syk

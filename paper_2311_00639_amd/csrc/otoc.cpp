@@ -1,0 +1,123 @@
+// Regularised OTOC of Eq. (2) by the random-state estimator of the supplement, computed as
+// the sum of the U-block and D-block chains ("+ swap UD"):
+//
+//   F_v(t) = <psi| e^{(it-b/8)H} W e^{-(it+b/4)H} V e^{(it-b/4)H} W e^{-(it+b/4)H} V e^{-bH/8} |psi>
+//
+// with W = chi_i, V = chi_j.  Every Majorana maps one parity block to the other, so reading
+// the chain from the right, for the block A of psi and the other block B:
+//   r0 = e^{-b H_A/8} psi_A,                       l  = r0
+//   r2 = e^{-b H_B/4} V_BA r0                      (t-independent)
+//   for increasing t:  r2 <- e^{-i dt H_B} r2,  l <- e^{-i dt H_A} l      (incremental)
+//   r4 = e^{(it - b/4) H_A} W_AB r2,  r6 = e^{(-it - b/4) H_B} V_BA r4
+//   F_A(t) = <l, W_AB r6> / 4          (1/4 = (1/sqrt 2)^4 from chi = gamma / sqrt 2)
+// since <psi_A| e^{(it-b/8)H_A} = (e^{(-it-b/8)H_A} psi_A)^dagger = (e^{-itH_A} r0)^dagger.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "krylov.hpp"
+#include "otoc.hpp"
+
+namespace syk {
+
+namespace {
+auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+}
+
+size_t otoc_workspace_bytes(uint64_t n, int m, size_t elem_bytes) {
+    return 4 * up(static_cast<size_t>(n) * 2 * elem_bytes) + krylov_workspace_bytes(n, m, elem_bytes);
+}
+
+// y = gamma_n block mapping `src` to the other block
+template <typename T>
+void apply_gamma(int N, int n, int src, const T *x, T *y, uint64_t amps, hipStream_t s) {
+    if (n == N - 1) {
+        // gamma_{N-1}^{UD} = -i (from D), gamma_{N-1}^{DU} = +i (from U)
+        launch_majorana<T>(0u, 0u, 0, 0.0, src == 0 ? 1.0 : -1.0, x, y, amps, s);
+    } else {
+        uint32_t bx, bz;
+        int bw;
+        block_majorana(N, n, bx, bz, bw);
+        launch_majorana<T>(bx, bz, bw, 1.0, 0.0, x, y, amps, s);
+    }
+}
+
+template <typename T>
+void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<double> &ts, const syk_otoc_opts &o,
+              std::vector<std::complex<double>> &F, syk_otoc_stats &st, char *ws, hipStream_t s) {
+    const uint64_t n = 1ULL << h.L;
+    const size_t vb = up(static_cast<size_t>(n) * 2 * sizeof(T));
+    T *l = reinterpret_cast<T *>(ws);
+    T *r2 = reinterpret_cast<T *>(ws + vb);
+    T *r4 = reinterpret_cast<T *>(ws + 2 * vb);
+    T *tmp = reinterpret_cast<T *>(ws + 3 * vb);
+    char *kws = ws + 4 * vb;
+    const DeviceTables *tb[2] = {&h.tables(0), &h.tables(1)};
+    KrylovRun<T> kr[2] = {KrylovRun<T>(*tb[0], n, o.krylov.m, kws, s), KrylovRun<T>(*tb[1], n, o.krylov.m, kws, s)};
+    ApplyTimer timer;
+    if (o.profile) {
+        kr[0].set_timer(&timer);
+        kr[1].set_timer(&timer);
+    }
+    const int nt = static_cast<int>(ts.size());
+    F.assign(nt, 0.0);
+    std::vector<double> hd(2);
+    using cd = std::complex<double>;
+    auto prop = [&](int blk, cd z, T *v) {
+        syk_krylov_stats ks{};
+        kr[blk].run(z, v, v, o.krylov, ks);
+        st.matvecs += ks.matvecs;
+        st.substeps += ks.substeps;
+        st.max_err_est = std::max(st.max_err_est, ks.err_est);
+    };
+    for (int v = 0; v < o.nvec; ++v) {
+        for (int A = 0; A < 2; ++A) {
+            const int B = 1 - A;
+            // psi: the A part into l, the B part into tmp (discarded), normalised over both
+            T *pu = (A == 0) ? l : tmp;
+            T *pd = (A == 0) ? tmp : l;
+            launch_haar_raw<T>(o.state_seed, v, h.L, pu, pd, kr[0].partials(), kr[0].n_part(), s);
+            launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 1, kr[0].scratch(), s);
+            launch_scale_pair<T>(pu, pd, n, kr[0].scratch(), s);
+            prop(A, cd(-beta / 8.0, 0.0), l);                     // l = r0
+            apply_gamma<T>(h.N, j, A, l, r2, n, s);                // V_BA r0
+            prop(B, cd(-beta / 4.0, 0.0), r2);                     // r2
+            double tprev = 0.0;
+            for (int k = 0; k < nt; ++k) {
+                const double t = ts[k];
+                const double dt = t - tprev;
+                if (dt > 0.0) {
+                    prop(B, cd(0.0, -dt), r2);
+                    prop(A, cd(0.0, -dt), l);
+                }
+                tprev = t;
+                apply_gamma<T>(h.N, i, B, r2, r4, n, s);           // W_AB r2
+                prop(A, cd(-beta / 4.0, t), r4);                   // r4
+                apply_gamma<T>(h.N, j, A, r4, tmp, n, s);          // V_BA r4
+                prop(B, cd(-beta / 4.0, -t), tmp);                 // r6
+                apply_gamma<T>(h.N, i, B, tmp, r4, n, s);          // W_AB r6
+                launch_dot_partials<T>(l, r4, n, kr[0].partials(), kr[0].n_part(), s);
+                launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 2, kr[0].scratch(), s);
+                SYK_HIP(hipMemcpyAsync(hd.data(), kr[0].scratch(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+                SYK_HIP(hipStreamSynchronize(s));
+                if (!std::isfinite(hd[0]) || !std::isfinite(hd[1])) fail(SYK_ENUMERIC, "non-finite OTOC overlap");
+                F[k] += 0.25 * cd(hd[0], hd[1]);
+            }
+        }
+    }
+    for (auto &f : F) f /= static_cast<double>(o.nvec);
+    SYK_HIP(hipStreamSynchronize(s));
+    timer.flush();
+    st.apply_ms += timer.ms;
+    st.apply_launches += timer.launches;
+}
+
+template void otoc_run<float>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
+                              std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t);
+template void otoc_run<double>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
+                               std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t);
+template void apply_gamma<float>(int, int, int, const float *, float *, uint64_t, hipStream_t);
+template void apply_gamma<double>(int, int, int, const double *, double *, uint64_t, hipStream_t);
+
+}  // namespace syk

@@ -1,0 +1,329 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle on the same seeded inputs.
+
+Tolerances (derivations in DESIGN.md, "Tolerances"):
+* complex128 apply_H: ||y - y_ref|| / ||y_ref|| <= 1e-10 (stated target; observed ~1e-16).
+* complex64 apply_H: the input is rounded to complex64 first and the oracle evaluates the
+  rounded input in float64, so only the float32 accumulation of <= K terms differs:
+  per row |err| <= K u sum_a |c_a x[m^x_a]| with u = 2^-24; the test uses the norm-wise
+  bound 4e-6 relative and the row-wise bound K u sum_a |c_a x|.
+* Krylov propagators: requested tolerance 1e-12 (c128) or 1e-7 (c64) per propagation.
+* OTOC: 1e-9 absolute on F (c128), 1e-5 absolute on F (c64 states, double reductions).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2311_00639_amd as syk  # noqa: E402
+from oracle import dense, ensemble, haar, matfree  # noqa: E402
+from tests import inputs  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+U24 = 2.0 ** -24
+
+
+def dev(a, dtype):
+    t = torch.from_numpy(np.ascontiguousarray(a.astype(np.complex128)))
+    return t.to(dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().to("cpu").numpy().astype(np.complex128)
+
+
+def cdt(dt):
+    return torch.complex64 if dt == syk.C64 else torch.complex128
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+# --------------------------------------------------------------------------- apply_H, small N
+@pytest.mark.parametrize("N,k,seed", [(6, 1, 5), (10, 21, 2), (12, 3, 7), (16, 4, 1), (20, 4, 20)])
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+@pytest.mark.parametrize("blk", [0, 1])
+def test_apply_h_vs_dense(N, k, seed, dt, blk):
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    Hb = dense.blocks(dense.hamiltonian(N, subs, J))[blk]
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    n = Hb.shape[0]
+    x = inputs.complex_vector(n, seed + 100)[0]
+    xd = dev(x, cdt(dt))
+    xr = host(xd)                           # the rounded input the GPU sees
+    yd = torch.empty_like(xd)
+    syk.apply_H(h, blk, xd, yd)
+    y = host(yd)
+    yref = Hb @ xr
+    if dt == syk.C128:
+        assert rel(y, yref) <= 1e-10
+        assert np.abs(y - yref).max() <= 1e-13 * np.abs(yref).max()
+    else:
+        assert rel(y, yref) <= 4e-6
+        bound = len(subs) * U24 * (np.abs(Hb) @ np.abs(xr)) + 1e-30
+        assert np.all(np.abs(y - yref) <= bound)
+
+
+def test_apply_h_many_vectors_with_stride():
+    """nvec > 1 with a leading dimension larger than the block (a ragged stride)."""
+    N, k, seed = 14, 3, 9
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    HU = dense.blocks(dense.hamiltonian(N, subs, J))[0]
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    n = HU.shape[0]
+    nvec, ld = 5, n + 37
+    X = np.zeros((nvec, ld), dtype=np.complex128)
+    X[:, :n] = inputs.complex_vector(n, 5, nvec)
+    X[:, n:] = 7.0                      # padding must be ignored and left untouched
+    xd = dev(X, torch.complex128)
+    yd = torch.full_like(xd, 3.0 + 0j)
+    syk.apply_H(h, 0, xd, yd, nvec=nvec, ld=ld)
+    Y = host(yd)
+    for v in range(nvec):
+        assert rel(Y[v, :n], HU @ X[v, :n]) <= 1e-13
+    assert np.all(Y[:, n:] == 3.0)
+
+
+def test_apply_h_repeatable_bitwise():
+    h = syk.create_hamiltonian(24, 4, 2, 1)
+    n = 1 << 11
+    xd = dev(inputs.complex_vector(n, 3)[0], torch.complex128)
+    a = torch.empty_like(xd)
+    b = torch.empty_like(xd)
+    syk.apply_H(h, 1, xd, a)
+    syk.apply_H(h, 1, xd, b)
+    assert torch.equal(a, b)
+
+
+# --------------------------------------------------------------------------- apply_H, large N
+def _sampled_rows_check(N, k, seed, dt, blk, nrows=3000):
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    n = 1 << (N // 2 - 1)
+    x = inputs.complex_vector(n, seed + 1)[0]
+    xd = dev(x, cdt(dt))
+    del x
+    yd = torch.empty_like(xd)
+    syk.apply_H(h, blk, xd, yd)
+    rows = inputs.row_sample(n, nrows, seed + 2)
+    xr = host(xd)
+    del xd
+    rows_t = torch.from_numpy(rows.astype(np.int64)).to("cuda")
+    y = host(yd[rows_t])
+    terms = matfree.block_terms(N, subs, J, blk)
+    yref = matfree.apply_rows(terms, lambda idx: xr[idx.astype(np.int64)], rows)
+    mag = matfree.apply_rows([(lab, abs(c)) for lab, c in terms], lambda idx: np.abs(xr[idx.astype(np.int64)]),
+                             rows).real
+    return y, yref, mag, len(subs)
+
+
+@pytest.mark.parametrize("blk", [0, 1])
+def test_apply_h_sampled_rows_N48_c128(blk):
+    y, yref, mag, K = _sampled_rows_check(48, 4, 48, syk.C128, blk)
+    assert rel(y, yref) <= 1e-10
+    assert np.all(np.abs(y - yref) <= 1e-14 * mag + 1e-300)
+
+
+def test_apply_h_sampled_rows_N56_c64():
+    """The N = 56, k = 4 (K = 224) block of the benchmark, complex64, same launch path."""
+    y, yref, mag, K = _sampled_rows_check(56, 4, 56, syk.C64, 0, nrows=2000)
+    assert rel(y, yref) <= 4e-6
+    assert np.all(np.abs(y - yref) <= K * U24 * mag)
+
+
+def test_apply_h_hermitian_N40():
+    """<u, H v> = conj <v, H u> for Haar-like u, v (exact up to rounding)."""
+    h = syk.create_hamiltonian(40, 4, 4, 40)
+    n = 1 << 19
+    U = dev(inputs.complex_vector(n, 1)[0], torch.complex128)
+    V = dev(inputs.complex_vector(n, 2)[0], torch.complex128)
+    HU = torch.empty_like(U)
+    HV = torch.empty_like(V)
+    syk.apply_H(h, 0, U, HU)
+    syk.apply_H(h, 0, V, HV)
+    a = torch.vdot(U, HV).item()
+    b = torch.vdot(V, HU).item()
+    assert abs(a - b.conjugate()) <= 1e-12 * abs(a)
+    # ||H v||^2 concentrates at (sum J^2 / 16) ||v||^2
+    r = torch.vdot(HV, HV).real.item() / torch.vdot(V, V).real.item()
+    assert abs(r / (h.info()["sum_J2"] / 16) - 1) < 0.05
+
+
+# --------------------------------------------------------------------------- Haar states
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_haar_state_vs_oracle_N16(dt):
+    N = 16
+    n = 1 << (N // 2 - 1)
+    pu = torch.empty(n, dtype=cdt(dt), device="cuda")
+    pd = torch.empty_like(pu)
+    syk.haar_state(N, 1001, 3, pu, pd)
+    ref = haar.haar_state(N, 1001, 3)
+    got = np.concatenate([host(pu), host(pd)])
+    tol = 1e-14 if dt == syk.C128 else 2e-7
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_haar_state_sampled_N48():
+    N = 48
+    n = 1 << (N // 2 - 1)
+    pu = torch.empty(n, dtype=torch.complex128, device="cuda")
+    pd = torch.empty_like(pu)
+    syk.haar_state(N, 4800, 0, pu, pd)
+    nrm = math.sqrt(haar.raw_norm2(N, 4800, 0))
+    idx = inputs.row_sample(2 * n, 2000, 1)
+    full = torch.cat([pu, pd])
+    got = host(full[torch.from_numpy(idx.astype(np.int64)).to("cuda")])
+    ref = haar.raw_amplitudes(4800, 0, idx) / nrm
+    assert np.abs(got - ref).max() <= 1e-14 * np.abs(ref).max()
+    assert abs(torch.vdot(full, full).real.item() - 1) < 1e-12
+
+
+# --------------------------------------------------------------------------- Majorana insertions
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_majorana_blocks_vs_dense(dt):
+    N = 12
+    g = dense.gammas(N)
+    h2 = g[0].shape[0] // 2
+    x = inputs.complex_vector(h2, 8)[0]
+    xd = dev(x, cdt(dt))
+    xr = host(xd)
+    tol = 1e-15 if dt == syk.C128 else 1e-6
+    for n in range(N):
+        for src in (0, 1):
+            yd = torch.empty_like(xd)
+            syk.apply_majorana(N, n, src, xd, yd, scale=0.5 - 0.25j)
+            block = g[n][h2:, :h2] if src == 0 else g[n][:h2, h2:]
+            assert np.abs(host(yd) - (0.5 - 0.25j) * block @ xr).max() <= tol
+
+
+# --------------------------------------------------------------------------- Krylov propagator
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+@pytest.mark.parametrize("z", [-0.3j, -7.0j, -1.25, 3j - 0.7, -20j - 5.0])
+def test_krylov_expm_vs_eigh(dt, z):
+    N, k, seed = 16, 4, 1
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    HD = dense.blocks(dense.hamiltonian(N, subs, J))[1]
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    v = inputs.complex_vector(HD.shape[0], 4)[0]
+    vd = dev(v, cdt(dt))
+    vr = host(vd)
+    out = torch.empty_like(vd)
+    st = syk.krylov_expm(h, 1, z, vd, out, m=30)
+    ref = dense.Eig(HD).expm_apply(z, vr)
+    tol = 1e-10 if dt == syk.C128 else 1e-5
+    assert rel(host(out), ref) <= tol
+    assert st["matvecs"] >= 1 and st["substeps"] >= 1
+
+
+def test_krylov_in_place_and_unitary():
+    h = syk.create_hamiltonian(30, 4, 4, 3)
+    n = 1 << 14
+    vd = dev(inputs.complex_vector(n, 6)[0], torch.complex128)
+    n0 = torch.linalg.vector_norm(vd).item()
+    w = vd.clone()
+    syk.krylov_expm(h, 0, -4.0j, w, w, m=30)
+    assert abs(torch.linalg.vector_norm(w).item() / n0 - 1) < 1e-11
+    # composition: e^{-2iH} e^{-2iH} v = e^{-4iH} v
+    a = vd.clone()
+    syk.krylov_expm(h, 0, -2.0j, a, a)
+    syk.krylov_expm(h, 0, -2.0j, a, a)
+    assert (torch.linalg.vector_norm(a - w) / n0).item() < 1e-10
+
+
+def test_krylov_single_term_breakdown_N48():
+    """H = (J/4) P with P^2 = 1: e^{-iHt} v = cos(Jt/4) v - i sin(Jt/4) P v exactly; the
+    Krylov space has dimension 2 (breakdown)."""
+    N = 48
+    h = syk.create_hamiltonian(N, 4, 1.0 / N, 77)
+    Jv = float(h.terms()["J"][0])
+    n = 1 << (N // 2 - 1)
+    vd = dev(inputs.complex_vector(n, 9)[0], torch.complex128)
+    Hv = torch.empty_like(vd)
+    syk.apply_H(h, 0, vd, Hv)
+    t = 3.7
+    a = Jv / 4
+    out = torch.empty_like(vd)
+    st = syk.krylov_expm(h, 0, -1j * t, vd, out, m=10)
+    ref = math.cos(a * t) * vd - 1j * math.sin(a * t) * (Hv / a)
+    assert (torch.linalg.vector_norm(out - ref) / torch.linalg.vector_norm(ref)).item() < 1e-12
+    assert st["breakdown"] == 1 and st["matvecs"] <= 10
+
+
+# --------------------------------------------------------------------------- OTOC
+def _oracle_otoc(N, k, seed, i, j, beta, ts, state_seed, nvec=1):
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    H = dense.hamiltonian(N, subs, J)
+    ch = dense.chis(N)
+    F = np.array([dense.otoc_state(H, ch[i], ch[j], beta, ts, haar.haar_state(N, state_seed, v))
+                  for v in range(nvec)])
+    return dense.normalise_curves(F)
+
+
+@pytest.mark.parametrize("i,j", [(1, 2), (15, 14)])
+@pytest.mark.parametrize("beta", [0.0, 5.0])
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_otoc_config_N16_vs_oracle(i, j, beta, dt):
+    """N = 16, k = 4 (K = 64), one realisation, one Haar state, m = 30, t = 0:0.1:10."""
+    ts = np.round(np.arange(101) * 0.1, 10)
+    raw, nrm, im = _oracle_otoc(16, 4, 1, i, j, beta, ts, 1001)
+    h = syk.create_hamiltonian(16, 4, 4, 1)
+    g_raw, g_nrm, g_im, st = syk.otoc(h, i, j, beta, ts, nvec=1, state_seed=1001, dtype=dt, m=30)
+    tol = 1e-9 if dt == syk.C128 else 1e-5
+    assert np.abs(g_raw - raw).max() <= tol
+    assert np.abs(g_nrm - nrm).max() <= tol / abs(raw[0]) * 2
+    assert np.abs(g_im - im).max() <= tol
+    assert st["matvecs"] > 0
+
+
+def test_otoc_two_vectors_ratio_of_sums():
+    ts = [0.0, 0.5, 1.5]
+    raw, nrm, im = _oracle_otoc(12, 3, 5, 11, 10, 2.0, ts, 77, nvec=2)
+    h = syk.create_hamiltonian(12, 4, 3, 5)
+    g_raw, g_nrm, g_im, _ = syk.otoc(h, 11, 10, 2.0, ts, nvec=2, state_seed=77, dtype=syk.C128)
+    assert np.abs(g_raw - raw).max() < 1e-10 and np.abs(g_nrm - nrm).max() < 1e-9
+
+
+def test_otoc_t_grid_without_zero():
+    """F_norm is normalised by t = 0 even when the grid does not start at 0."""
+    ts = [0.4, 0.9]
+    raw, nrm, _ = _oracle_otoc(12, 3, 6, 1, 4, 1.0, [0.0] + ts, 5)
+    h = syk.create_hamiltonian(12, 4, 3, 6)
+    g_raw, g_nrm, _, _ = syk.otoc(h, 1, 4, 1.0, ts, state_seed=5, dtype=syk.C128)
+    assert np.abs(g_raw - raw[1:]).max() < 1e-10 and np.abs(g_nrm - nrm[1:]).max() < 1e-9
+
+
+@pytest.mark.parametrize("N,dt", [(48, syk.C128), (56, syk.C64)])
+def test_otoc_single_term_closed_forms_large_N(N, dt):
+    """K = 1: Re F = -cos(J t)/4 when both Majoranas are in the term (any beta, any psi),
+    F = -1/4 when exactly one is, F_norm = 1 when neither is."""
+    h = syk.create_hamiltonian(N, 4, 1.0 / N, 5)
+    T = h.terms()
+    term = [int(v) for v in T["ijkl"][0]]
+    Jv = float(T["J"][0])
+    ts = np.array([0.0, 0.7, 2.5, 6.0])
+    tol = 1e-9 if dt == syk.C128 else 1e-5
+    others = [n for n in range(N) if n not in term]
+    raw, nrm, _, _ = syk.otoc(h, term[0], term[2], 4.0, ts, state_seed=3, dtype=dt, m=8)
+    assert np.abs(raw + np.cos(Jv * ts) / 4).max() <= tol
+    raw, _, _, _ = syk.otoc(h, term[1], others[0], 4.0, ts, state_seed=3, dtype=dt, m=8)
+    assert np.abs(raw + 0.25).max() <= tol
+    _, nrm, _, _ = syk.otoc(h, others[0], others[1], 4.0, ts, state_seed=3, dtype=dt, m=8)
+    assert np.abs(nrm - 1).max() <= 2 * tol
+
+
+def test_otoc_beta0_t0_minus_quarter_N40():
+    h = syk.create_hamiltonian(40, 4, 4, 8)
+    raw, _, im, _ = syk.otoc(h, 39, 38, 0.0, [0.0], state_seed=1, dtype=syk.C128)
+    assert abs(raw[0] + 0.25) < 1e-12 and abs(im[0]) < 1e-12
+
+
+def test_otoc_rejects_bad_arguments():
+    h = syk.create_hamiltonian(12, 4, 3, 5)
+    for args in ((3, 3, 1.0, [0.0]), (0, 12, 1.0, [0.0]), (0, 1, -1.0, [0.0]), (0, 1, 1.0, [0.5, 0.2])):
+        with pytest.raises(syk.SykError) as e:
+            syk.otoc(h, *args, dtype=syk.C128)
+        assert e.value.status == 1
