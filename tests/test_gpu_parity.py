@@ -17,7 +17,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 import paper_2311_00639_amd as syk  # noqa: E402
-from oracle import dense, ensemble, haar, matfree  # noqa: E402
+from oracle import dense, ensemble, haar, matfree, pauli  # noqa: E402
 from tests import inputs  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -116,8 +116,10 @@ def _sampled_rows_check(N, k, seed, dt, blk, nrows=3000):
     y = host(yd[rows_t])
     terms = matfree.block_terms(N, subs, J, blk)
     yref = matfree.apply_rows(terms, lambda idx: xr[idx.astype(np.int64)], rows)
-    mag = matfree.apply_rows([(lab, abs(c)) for lab, c in terms], lambda idx: np.abs(xr[idx.astype(np.int64)]),
-                             rows).real
+    # sum_a |c_a| |x[m ^ x_a]|: same flips, all matrix-element phases dropped (Y -> X, Z -> I)
+    flips = [(tuple(pauli.X if lab in (pauli.X, pauli.Y) else pauli.I for lab in labels), abs(c))
+             for labels, c in terms]
+    mag = matfree.apply_rows(flips, lambda idx: np.abs(xr[idx.astype(np.int64)]), rows).real
     return y, yref, mag, len(subs)
 
 
@@ -125,7 +127,7 @@ def _sampled_rows_check(N, k, seed, dt, blk, nrows=3000):
 def test_apply_h_sampled_rows_N48_c128(blk):
     y, yref, mag, K = _sampled_rows_check(48, 4, 48, syk.C128, blk)
     assert rel(y, yref) <= 1e-10
-    assert np.all(np.abs(y - yref) <= 1e-14 * mag + 1e-300)
+    assert np.all(np.abs(y - yref) <= K * 2.0 ** -52 * mag)
 
 
 def test_apply_h_sampled_rows_N56_c64():
