@@ -137,7 +137,9 @@ typedef struct {
 } syk_krylov_stats;
 
 /* Fill `o` with defaults for dtype dt (m = 30, tol = 1e-12 for C128 / 1e-7 for C64,
- * reorth = 1, max_substeps = 0). */
+ * reorth = 0, max_substeps = 0).  With reorth = 0 on blocks served by the tiled kernel,
+ * each Lanczos step is one fused apply (w = H v_j - beta v_{j-1} plus the alpha/beta sums)
+ * and one normalising pass. */
 void syk_krylov_default_opts(syk_dtype dt, syk_krylov_opts *o);
 
 /* out = e^{z H_blk} v, z = z_re + i z_im, by Lanczos with restarts (the restarted Krylov
@@ -161,6 +163,10 @@ typedef struct {
     syk_dtype dtype;       /* state-vector precision; reductions are double either way */
     syk_krylov_opts krylov;
     int profile;           /* 1: time every apply_H launch with HIP events on `stream` */
+    int layout;            /* -1: internal vector layout chosen by the planner (see
+                              syk_plan_describe); r >= 0: bit rotation r (0 = standard order) */
+    int autotune;          /* 1: before the first run of this handle/precision/device, time the
+                              tiled apply_H variants and keep the fastest (syk_autotune) */
 } syk_otoc_opts;
 
 typedef struct {
@@ -196,6 +202,30 @@ syk_status syk_workspace_bytes(int N, int m, syk_dtype dt, int nvec, uint64_t *b
  * c_re, c_im: host, n doubles.  Errors: EINVAL (n < 1 or > 1024, null), ENUMERIC. */
 syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, double z_re, double z_im,
                             double *c_re, double *c_im);
+
+/* Launch plan of the tiled apply_H kernel for one block (host-only; no GPU needed).
+ * Blocks of 2^L amplitudes with L >= tile_bits + 5 are served by the tiled kernel: output
+ * tiles of 2^tile_bits amplitudes, terms grouped by partner tile (n_groups groups), tiles
+ * mapped to workgroups so that the ones resident on one XCD form a coset of a 5-dim
+ * subspace (classes5 = partner-tile classes modulo it) and those on the GPU one of an
+ * 8-dim subspace (classes8).  rot is the vector layout: index bit b holds qubit
+ * (b + rot) mod L.  layout = -1 asks for the planner's choice (the layout syk_otoc uses by
+ * default), layout >= 0 for that rotation. */
+typedef struct {
+    int tiled;             /* 0: the block is served by the per-amplitude gather kernel */
+    int variant;           /* compiled kernel variant in use (default or tuned) */
+    int tile_bits, rot, n_groups, classes5, classes8;
+    uint64_t n_tiles;
+} syk_plan_desc;
+syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, syk_plan_desc *out);
+
+/* Schedule autotuner: time each compiled variant of the tiled apply_H kernel (tile size,
+ * LDS buffering, prefetch depth; each in its planned layout) on this Hamiltonian and keep
+ * the fastest for the current device and precision.  *variant receives the choice (-1 if
+ * the block is not tiled); ms[v] (host, cap entries, may be NULL) the mean time of one
+ * apply with variant v (-1 where skipped).  Uses a library-owned workspace of two vectors.
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+syk_status syk_autotune(const syk_ham *h, syk_dtype dt, int *variant, float *ms, int cap, void *stream);
 
 /* Release the library's cached device workspaces on the current device. */
 syk_status syk_release_workspace(void);

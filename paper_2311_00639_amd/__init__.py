@@ -18,11 +18,13 @@ from ._lib import (  # noqa: F401
     KrylovOpts,
     apply_H,
     apply_majorana,
+    autotune,
     create_hamiltonian,
     haar_state,
     krylov_expm,
     library_path,
     otoc,
+    plan_describe,
     release_workspace,
     tridiag_expm,
     workspace_bytes,

@@ -21,7 +21,7 @@ class SykError(RuntimeError):
 
 
 if not os.path.exists(_LIBPATH):
-    raise ImportError(f"libsyk.so not built ({_LIBPATH}); run `python -m paper_2311_00639_amd.build`")
+    raise ImportError(f"libsyk.so not built ({_LIBPATH}); run `python paper_2311_00639_amd/build.py`")
 _lib = ct.CDLL(_LIBPATH)
 
 
@@ -44,7 +44,13 @@ class KrylovStats(ct.Structure):
 
 class OtocOpts(ct.Structure):
     _fields_ = [("nvec", ct.c_int), ("state_seed", ct.c_uint64), ("dtype", ct.c_int), ("krylov", KrylovOpts),
-                ("profile", ct.c_int)]
+                ("profile", ct.c_int), ("layout", ct.c_int), ("autotune", ct.c_int)]
+
+
+class PlanDesc(ct.Structure):
+    _fields_ = [("tiled", ct.c_int), ("variant", ct.c_int), ("tile_bits", ct.c_int), ("rot", ct.c_int),
+                ("n_groups", ct.c_int),
+                ("classes5", ct.c_int), ("classes8", ct.c_int), ("n_tiles", ct.c_uint64)]
 
 
 class OtocStats(ct.Structure):
@@ -67,6 +73,8 @@ _SIGS = {
     "syk_workspace_bytes": [_i, _i, _i, _i, ct.POINTER(_u64)],
     "syk_tridiag_expm": [_i, _dp, _dp, _d, _d, _dp, _dp],
     "syk_release_workspace": [],
+    "syk_plan_describe": [_vp, _i, _i, _i, ct.POINTER(PlanDesc)],
+    "syk_autotune": [_vp, _i, ct.POINTER(_i), ct.POINTER(ct.c_float), _i, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -205,7 +213,8 @@ def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None,
 
 
 def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_seed: int = 0, dtype: int = C128,
-         m: int = None, tol: float = None, reorth: int = None, profile: bool = False, stream=None):
+         m: int = None, tol: float = None, reorth: int = None, profile: bool = False, layout: int = -1,
+         autotune: bool = True, stream=None):
     """Regularised OTOC (Eq. (2)) by the random-state estimator.  Returns
     (F_raw, F_norm, F_imag, stats) with numpy float64 arrays."""
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
@@ -216,6 +225,8 @@ def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_
     o.dtype = dtype
     o.krylov = default_krylov_opts(dtype)
     o.profile = 1 if profile else 0
+    o.layout = layout
+    o.autotune = 1 if autotune else 0
     if m is not None:
         o.krylov.m = m
     if tol is not None:
@@ -249,6 +260,22 @@ def tridiag_expm(alpha, beta, z: complex) -> np.ndarray:
     dp = lambda v: v.ctypes.data_as(_dp)
     _check(_lib.syk_tridiag_expm(n, dp(a), dp(b) if b.size else None, z.real, z.imag, dp(cr), dp(ci)))
     return cr + 1j * ci
+
+
+def plan_describe(ham: Hamiltonian, block: int, dtype: int, layout: int = -1) -> dict:
+    """Launch plan of the tiled apply_H kernel (host-only)."""
+    d = PlanDesc()
+    _check(_lib.syk_plan_describe(ham.handle, block, dtype, layout, ct.byref(d)))
+    return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
+
+
+def autotune(ham: Hamiltonian, dtype: int, stream=None):
+    """Time the tiled apply_H variants on this Hamiltonian.  Returns (chosen variant,
+    per-variant ms per apply, -1 where skipped)."""
+    v = ct.c_int(-1)
+    ms = (ct.c_float * 16)()
+    _check(_lib.syk_autotune(ham.handle, dtype, ct.byref(v), ms, 16, _stream(stream)))
+    return v.value, [round(float(t), 4) for t in ms if t != -1.0]
 
 
 def release_workspace():

@@ -1,6 +1,6 @@
 """Build libsyk.so in-tree: host C++ with g++, HIP kernels with hipcc for gfx950.
 
-Usage: python -m paper_2311_00639_amd.build  (or call build())."""
+Usage: python paper_2311_00639_amd/build.py [-v]  (or __graft_entry__.build())."""
 import os
 import shutil
 import subprocess
@@ -12,8 +12,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsyk.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["terms.cpp", "runtime.cpp", "krylov.cpp", "otoc.cpp", "api.cpp"]
-HIP_SOURCES = ["kernels.hip"]
+HOST_SOURCES = ["terms.cpp", "runtime.cpp", "apply_plan.cpp", "krylov.cpp", "otoc.cpp", "api.cpp"]
+HIP_SOURCES = ["kernels.hip", "apply_tiled.hip"]
 
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-Wextra", "-Wno-unused-parameter",
               "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"), "-I" + CSRC,

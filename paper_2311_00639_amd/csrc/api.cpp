@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 
+#include "apply_plan.hpp"
 #include "krylov.hpp"
 #include "otoc.hpp"
 
@@ -128,13 +129,12 @@ syk_status syk_apply_H(const syk_ham *h, syk_block blk, syk_dtype dt, const void
         require(ld >= n_amps, "ld must be >= n_amps");
         check_device();
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
-        const auto &tb = H.tables(blk);
         if (dt == SYK_C64)
-            syk::launch_apply_h<float>(tb, static_cast<const float *>(x), static_cast<float *>(y),
-                                       static_cast<uint32_t>(n_amps), nvec, ld, as_stream(stream));
+            syk::apply_block<float>(H, blk, 0, static_cast<const float *>(x), static_cast<float *>(y), nvec, ld,
+                                    as_stream(stream));
         else
-            syk::launch_apply_h<double>(tb, static_cast<const double *>(x), static_cast<double *>(y),
-                                        static_cast<uint32_t>(n_amps), nvec, ld, as_stream(stream));
+            syk::apply_block<double>(H, blk, 0, static_cast<const double *>(x), static_cast<double *>(y), nvec, ld,
+                                     as_stream(stream));
     });
 }
 
@@ -153,12 +153,12 @@ syk_status syk_haar_state(int N, uint64_t state_seed, int v, syk_dtype dt, void 
         double *sum = part + np;
         hipStream_t s = as_stream(stream);
         if (dt == SYK_C64) {
-            syk::launch_haar_raw<float>(state_seed, v, N / 2 - 1, static_cast<float *>(psi_U),
+            syk::launch_haar_raw<float>(state_seed, v, N / 2 - 1, 0, static_cast<float *>(psi_U),
                                         static_cast<float *>(psi_D), part, np, s);
             syk::launch_reduce_partials(part, np, 1, sum, s);
             syk::launch_scale_pair<float>(static_cast<float *>(psi_U), static_cast<float *>(psi_D), n, sum, s);
         } else {
-            syk::launch_haar_raw<double>(state_seed, v, N / 2 - 1, static_cast<double *>(psi_U),
+            syk::launch_haar_raw<double>(state_seed, v, N / 2 - 1, 0, static_cast<double *>(psi_U),
                                          static_cast<double *>(psi_D), part, np, s);
             syk::launch_reduce_partials(part, np, 1, sum, s);
             syk::launch_scale_pair<double>(static_cast<double *>(psi_U), static_cast<double *>(psi_D), n, sum, s);
@@ -198,7 +198,7 @@ void syk_krylov_default_opts(syk_dtype dt, syk_krylov_opts *o) {
     if (!o) return;
     o->m = 30;
     o->tol = (dt == SYK_C64) ? 1e-7 : 1e-12;
-    o->reorth = 1;
+    o->reorth = 0;
     o->max_substeps = 0;
 }
 
@@ -214,18 +214,17 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
         check_opts(*o);
         check_device();
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
-        const auto &tb = H.tables(blk);
         syk_krylov_stats st{};
         auto &ws = syk::thread_workspace(0);
         hipStream_t s = as_stream(stream);
         const std::complex<double> z(z_re, z_im);
         if (dt == SYK_C64) {
             ws.ensure(syk::krylov_workspace_bytes(n_amps, o->m, sizeof(float)));
-            syk::KrylovRun<float> kr(tb, n_amps, o->m, ws.ptr(), s);
+            syk::KrylovRun<float> kr(H, blk, 0, n_amps, o->m, ws.ptr(), s);
             kr.run(z, static_cast<const float *>(v), static_cast<float *>(out), *o, st);
         } else {
             ws.ensure(syk::krylov_workspace_bytes(n_amps, o->m, sizeof(double)));
-            syk::KrylovRun<double> kr(tb, n_amps, o->m, ws.ptr(), s);
+            syk::KrylovRun<double> kr(H, blk, 0, n_amps, o->m, ws.ptr(), s);
             kr.run(z, static_cast<const double *>(v), static_cast<double *>(out), *o, st);
         }
         SYK_HIP(hipStreamSynchronize(s));
@@ -242,7 +241,9 @@ syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t
         require(nt >= 1, "nt must be >= 1");
         require(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
         require(o->nvec >= 1, "nvec must be >= 1");
+        require(o->autotune == 0 || o->autotune == 1, "autotune must be 0 or 1");
         require(o->dtype == SYK_C64 || o->dtype == SYK_C128, "invalid dtype");
+        require(o->layout >= -1 && o->layout < std::max(N / 2 - 1, 1), "layout must be -1 or a rotation in [0, L)");
         check_opts(o->krylov);
         for (int k = 0; k < nt; ++k) {
             require(std::isfinite(t[k]) && t[k] >= 0.0, "t must be finite and >= 0");
@@ -304,6 +305,65 @@ syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, doub
             c_re[i] = c[i].real();
             c_im[i] = c[i].imag();
         }
+    });
+}
+
+syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, syk_plan_desc *out) {
+    return guarded([&] {
+        require(h && out, "NULL argument");
+        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        require(layout >= -1 && layout < std::max(H.L, 1), "layout must be -1 or a rotation in [0, L)");
+        *out = syk_plan_desc{};
+        const bool c64 = dt == SYK_C64;
+        out->tiled = c64 ? syk::use_tiled<float>(H.L) : syk::use_tiled<double>(H.L);
+        if (!out->tiled) return;
+        const int var = c64 ? H.variant<float>() : H.variant<double>();
+        const syk::TiledVariant tv = c64 ? syk::tiled_variants<float>()[var] : syk::tiled_variants<double>()[var];
+        const int bt = tv.bt, rb = tv.rb;
+        out->tile_bits = bt;
+        out->variant = var;
+        const int rot = layout >= 0 ? layout : (c64 ? H.internal_rotation<float>(var) : H.internal_rotation<double>(var));
+        const syk::HostPlan hp = syk::build_host_plan(H.block_terms[blk], H.L, bt, rb, tv.nbuf, tv.pf, rot, c64 ? 8u : 16u);
+        // consistency: the tile map is a bijection and every term sits in one group
+        std::vector<char> seen(hp.n_tiles, 0);
+        for (uint32_t t : hp.tile_map) {
+            if (t >= hp.n_tiles || seen[t]) syk::fail(SYK_EDEVICE, "tile map is not a bijection");
+            seen[t] = 1;
+        }
+        if (hp.grp_first.back() != static_cast<uint32_t>(H.K)) syk::fail(SYK_EDEVICE, "groups do not cover all terms");
+        out->rot = rot;
+        int real_groups = 0;
+        for (int g = 0; g < hp.n_groups; ++g) real_groups += hp.grp_first[g + 1] > hp.grp_first[g];
+        out->n_groups = real_groups;
+        out->classes5 = hp.classes5;
+        out->classes8 = hp.classes8;
+        out->n_tiles = hp.n_tiles;
+    });
+}
+
+syk_status syk_autotune(const syk_ham *h, syk_dtype dt, int *variant, float *ms, int cap, void *stream) {
+    return guarded([&] {
+        require(h != nullptr, "NULL handle");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        check_device();
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        const uint64_t n = 1ULL << H.L;
+        const size_t es = (dt == SYK_C64) ? 2 * sizeof(float) : 2 * sizeof(double);
+        auto &ws = syk::thread_workspace(0);
+        ws.ensure(2 * n * es);
+        hipStream_t s = as_stream(stream);
+        std::vector<float> times;
+        int v = (dt == SYK_C64)
+                    ? syk::autotune<float>(H, reinterpret_cast<float *>(ws.ptr()),
+                                           reinterpret_cast<float *>(ws.ptr() + n * es), s, true, &times)
+                    : syk::autotune<double>(H, reinterpret_cast<double *>(ws.ptr()),
+                                            reinterpret_cast<double *>(ws.ptr() + n * es), s, true, &times);
+        SYK_HIP(hipStreamSynchronize(s));
+        if (variant) *variant = v;
+        if (ms)
+            for (int k = 0; k < cap; ++k) ms[k] = k < static_cast<int>(times.size()) ? times[k] : -1.0f;
     });
 }
 

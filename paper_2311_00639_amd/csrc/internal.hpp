@@ -5,7 +5,9 @@
 
 #include <cstdint>
 #include <cstddef>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -42,6 +44,49 @@ struct DeviceTables {            // per device, per block: real terms first, the
     int K = 0;
 };
 
+// Compiled variants of the tiled apply_H kernel: 2^bt amplitudes per output tile,
+// 2^rb register-held outputs per thread (2^(bt-rb) threads per workgroup), nbuf LDS
+// buffers of one partner tile each (at most 128 KiB of the 160 KiB per CU), pf = nbuf - 1
+// partner tiles in flight.  The autotuner times them on the actual Hamiltonian.
+struct TiledVariant {
+    int bt, rb, nbuf, pf;
+};
+template <typename T>
+const std::vector<TiledVariant> &tiled_variants();
+// variant used before (or without) autotuning
+template <typename T>
+int default_variant();
+// smallest block (in qubits) served by the tiled kernel
+constexpr int kTiledMinL = 18;
+
+// bit rotations within L bits: layout rotation s stores qubit (b + s) mod L at index bit b
+uint32_t rotr_bits(uint32_t v, int s, int L);
+uint32_t rotl_bits(uint32_t v, int s, int L);
+
+struct ApplyPlan {
+    int bt = 0, rb = 0, rot = 0, variant = 0;
+    uint32_t n_tiles = 0;
+    uint32_t *tile_map = nullptr;    // n_tiles: blockIdx -> output tile
+    int n_groups = 0;
+    uint32_t *grp_g = nullptr;       // n_groups: partner tile offset g = x >> BT
+    uint32_t *grp_first = nullptr;   // n_groups + 1: first term of each group
+    uint32_t *grp_mid = nullptr;     // n_groups: first i-phase term (real-phase terms come first)
+    uint32_t *meta = nullptr;        // K records of 4 + 2R dwords (see apply_tiled.hip)
+    float *c32 = nullptr;
+    double *c64 = nullptr;
+};
+
+// Optional epilogue of the tiled apply_H for one Lanczos step: y = H v_j - beta_{j-1} v_{j-1}
+// (vprev may be null, beta2_prev points at beta_{j-1}^2 on the device), and per-workgroup
+// partial sums (re <v_j,y>, im <v_j,y>, ||y||^2, ||v_j||^2) at partials[4 * blockIdx.x].
+template <typename T>
+struct LanczosFuse {
+    const T *vprev = nullptr;
+    const T *vcur = nullptr;
+    const double *beta2_prev = nullptr;
+    double *partials = nullptr;
+};
+
 // ------------------------------------------------------------------ host-side model
 uint64_t splitmix_mix(uint64_t z);
 
@@ -58,7 +103,17 @@ struct Hamiltonian {
 
     std::mutex dev_mu;
     std::vector<DeviceTables> dev[2];  // indexed by device ordinal
+    // plans keyed by (block, double?, device, rotation, variant)
+    std::map<std::tuple<int, int, int, int, int>, ApplyPlan> plans;
+    int rotation[2][8] = {{-1, -1, -1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1, -1, -1}};
+    std::map<std::pair<int, int>, int> tuned;                   // (double?, device) -> variant
     const DeviceTables &tables(int blk);
+    template <typename T>
+    const ApplyPlan &plan(int blk, int rot, int variant);
+    template <typename T>
+    int internal_rotation(int variant);   // layout used inside Krylov/OTOC runs (0 if not tiled)
+    template <typename T>
+    int variant();                        // tuned variant on the current device, else the default
     ~Hamiltonian();
 };
 
@@ -87,13 +142,32 @@ class DeviceBuffer {
 // per-(device, thread) cached workspace used by the convenience entry points
 DeviceBuffer &thread_workspace(int slot);
 
+// y = H_blk x on the device: tiled kernel for large blocks, gather kernel otherwise
+template <typename T>
+inline bool use_tiled(int L) {
+    return L >= kTiledMinL;
+}
+template <typename T>
+void apply_block(Hamiltonian &h, int blk, int rot, const T *x, T *y, int nvec, uint64_t ld, hipStream_t s);
+// y = H_blk x with the fused Lanczos epilogue (tiled blocks only); returns the number of
+// partials written (one per tile)
+template <typename T>
+int apply_block_lanczos(Hamiltonian &h, int blk, int rot, const T *x, T *y, const LanczosFuse<T> &lf,
+                        hipStream_t s);
+// upper bound on the partials apply_block_lanczos writes for a block of 2^L amplitudes
+inline uint64_t lanczos_partials_max(int L) { return 1ULL << (L > 10 ? L - 10 : 0); }
+// time the tiled-kernel variants and keep the fastest; returns it (-1: block not tiled)
+template <typename T>
+int autotune(Hamiltonian &h, T *x, T *y, hipStream_t s, bool force, std::vector<float> *times = nullptr);
+
 // ------------------------------------------------------------------ kernels (HIP side)
 // All launchers enqueue on `s` and never synchronise.
 template <typename T>
 void launch_apply_h(const DeviceTables &tb, const T *x, T *y, uint32_t n_amps, int nvec, uint64_t ld,
                     hipStream_t s);
+// psi in layout rotation `rot`: index p holds standard amplitude rotl(p, rot)
 template <typename T>
-void launch_haar_raw(uint64_t state_seed, int v, int L, T *psi_U, T *psi_D, double *partials, int n_part,
+void launch_haar_raw(uint64_t state_seed, int v, int L, int rot, T *psi_U, T *psi_D, double *partials, int n_part,
                      hipStream_t s);
 template <typename T>
 void launch_scale_pair(T *a, T *b, uint64_t n, const double *inv_norm_dev, hipStream_t s);
@@ -117,6 +191,13 @@ void launch_lanczos_orth2(T *w, const T *vcur, const double *alpha, uint64_t n, 
                           hipStream_t s);
 template <typename T>
 void launch_lanczos_normalize(T *w, const double *beta, uint64_t n, hipStream_t s);
+// sums[0..4) = (re <v,w>, im <v,w>, ||w||^2, ||v||^2) -> alpha = (re, im) at alpha_out[0..2),
+// beta^2 = ||w - alpha_re v||^2 at beta2_out (expanded in the sums)
+void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_out, double *beta2_out,
+                            hipStream_t s);
+// w <- (w - alpha_re v) / beta, beta = sqrt(beta2[0]); zero if beta underflows
+template <typename T>
+void launch_lanczos_update(T *w, const T *v, const double *alpha, const double *beta2, uint64_t n, hipStream_t s);
 template <typename T>
 void launch_scale_copy(const T *src, T *dst, uint64_t n, double scale, hipStream_t s);
 template <typename T>

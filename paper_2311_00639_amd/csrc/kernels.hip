@@ -116,15 +116,18 @@ __device__ inline double2 haar_amp(uint64_t base, uint64_t n) {
     return double2{r * cs, r * sn};
 }
 
+// index b of the stored (layout-rotated) block holds standard block index m = rotl(b, rot)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) haar_raw(uint64_t base, int L, V2<T> *__restrict__ pu,
+__global__ void __launch_bounds__(kBlock) haar_raw(uint64_t base, int L, int rot, V2<T> *__restrict__ pu,
                                                    V2<T> *__restrict__ pd, double *__restrict__ partials) {
     const uint64_t h = 1ULL << L;
+    const uint64_t mask = h - 1;
     double acc[1] = {0.0};
     for (uint64_t b = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; b < h;
          b += static_cast<uint64_t>(gridDim.x) * kBlock) {
-        const double2 a = haar_amp(base, b);
-        const double2 d = haar_amp(base, h + b);
+        const uint64_t m = rot ? (((b << rot) | (b >> (L - rot))) & mask) : b;
+        const double2 a = haar_amp(base, m);
+        const double2 d = haar_amp(base, h + m);
         acc[0] += a.x * a.x + a.y * a.y + d.x * d.x + d.y * d.y;
         pu[b] = V2<T>{static_cast<T>(a.x), static_cast<T>(a.y)};
         pd[b] = V2<T>{static_cast<T>(d.x), static_cast<T>(d.y)};
@@ -133,10 +136,11 @@ __global__ void __launch_bounds__(kBlock) haar_raw(uint64_t base, int L, V2<T> *
 }
 
 template <typename T>
-void launch_haar_raw(uint64_t state_seed, int v, int L, T *psi_U, T *psi_D, double *partials, int n_part,
+void launch_haar_raw(uint64_t state_seed, int v, int L, int rot, T *psi_U, T *psi_D, double *partials, int n_part,
                      hipStream_t s) {
     const uint64_t base = splitmix_mix(state_seed + static_cast<uint64_t>(v + 1) * 0x9E3779B97F4A7C15ULL);
-    hipLaunchKernelGGL(haar_raw<T>, dim3(n_part), dim3(kBlock), 0, s, base, L, reinterpret_cast<V2<T> *>(psi_U),
+    hipLaunchKernelGGL(haar_raw<T>, dim3(n_part), dim3(kBlock), 0, s, base, L, rot % (L > 0 ? L : 1),
+                       reinterpret_cast<V2<T> *>(psi_U),
                        reinterpret_cast<V2<T> *>(psi_D), partials);
     SYK_HIP(hipGetLastError());
 }
@@ -332,6 +336,54 @@ void launch_lanczos_normalize(T *w, const double *norm2, uint64_t n, hipStream_t
     SYK_HIP(hipGetLastError());
 }
 
+__global__ void __launch_bounds__(kBlock) lanczos_scalars_kernel(const double *__restrict__ partials, int n_part,
+                                                                 double *__restrict__ alpha_out,
+                                                                 double *__restrict__ beta2_out) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = threadIdx.x; p < n_part; p += kBlock)
+        for (int k = 0; k < 4; ++k) acc[k] += partials[static_cast<size_t>(p) * 4 + k];
+    __shared__ double tot[4];
+    block_sum<4>(acc, tot);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double a = tot[0];
+        alpha_out[0] = a;
+        alpha_out[1] = tot[1];
+        const double b2 = tot[2] - 2.0 * a * tot[0] + a * a * tot[3];
+        beta2_out[0] = b2 > 0.0 ? b2 : 0.0;
+    }
+}
+
+void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_out, double *beta2_out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_scalars_kernel, dim3(1), dim3(kBlock), 0, s, partials, n_part, alpha_out, beta2_out);
+    SYK_HIP(hipGetLastError());
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lanczos_update(V2<T> *__restrict__ w, const V2<T> *__restrict__ v,
+                                                         const double *__restrict__ alpha,
+                                                         const double *__restrict__ beta2, uint64_t n) {
+    const double b = sqrt(beta2[0]);
+    const T inv = (b > 1e-300) ? static_cast<T>(1.0 / b) : T(0);
+    const T al = static_cast<T>(alpha[0]);
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = w[i];
+        const V2<T> c = v[i];
+        u.x = (u.x - al * c.x) * inv;
+        u.y = (u.y - al * c.y) * inv;
+        w[i] = u;
+    }
+}
+
+template <typename T>
+void launch_lanczos_update(T *w, const T *v, const double *alpha, const double *beta2, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_update<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
+                       reinterpret_cast<const V2<T> *>(v), alpha, beta2, n);
+    SYK_HIP(hipGetLastError());
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) scale_copy(const V2<T> *__restrict__ src, V2<T> *__restrict__ dst,
                                                      uint64_t n, double scale) {
@@ -433,7 +485,7 @@ void launch_subtract_proj(T *w, const T *basis, uint64_t stride, int nb, const d
 // ------------------------------------------------------------------ instantiations
 #define SYK_INST(T)                                                                                                \
     template void launch_apply_h<T>(const DeviceTables &, const T *, T *, uint32_t, int, uint64_t, hipStream_t);   \
-    template void launch_haar_raw<T>(uint64_t, int, int, T *, T *, double *, int, hipStream_t);                    \
+    template void launch_haar_raw<T>(uint64_t, int, int, int, T *, T *, double *, int, hipStream_t);                    \
     template void launch_scale_pair<T>(T *, T *, uint64_t, const double *, hipStream_t);                           \
     template void launch_majorana<T>(uint32_t, uint32_t, int, double, double, const T *, T *, uint64_t,            \
                                      hipStream_t);                                                                 \
@@ -443,6 +495,7 @@ void launch_subtract_proj(T *w, const T *basis, uint64_t stride, int nb, const d
                                           hipStream_t);                                                            \
     template void launch_lanczos_orth2<T>(T *, const T *, const double *, uint64_t, double *, int, hipStream_t);   \
     template void launch_lanczos_normalize<T>(T *, const double *, uint64_t, hipStream_t);                         \
+    template void launch_lanczos_update<T>(T *, const T *, const double *, const double *, uint64_t, hipStream_t); \
     template void launch_scale_copy<T>(const T *, T *, uint64_t, double, hipStream_t);                             \
     template void launch_combine<T>(const T *, uint64_t, int, const double *, T *, uint64_t, hipStream_t);         \
     template void launch_subtract_proj<T>(T *, const T *, uint64_t, int, const double *, uint64_t, hipStream_t);   \

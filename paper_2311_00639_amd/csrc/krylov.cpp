@@ -138,17 +138,20 @@ void ApplyTimer::flush() {
 }
 
 // ------------------------------------------------------------------ Lanczos driver
+static int log2_of(uint64_t n) { return 63 - __builtin_clzll(n); }
+
 size_t krylov_workspace_bytes(uint64_t n, int m, size_t elem_bytes) {
     const size_t vec = static_cast<size_t>(n) * 2 * elem_bytes;
     const size_t part = static_cast<size_t>(reduction_blocks(n)) * 2 * (m + 2) * sizeof(double);
     const size_t scal = static_cast<size_t>(8 * (m + 4)) * sizeof(double);
+    const size_t fused = static_cast<size_t>(lanczos_partials_max(log2_of(n))) * 4 * sizeof(double);
     auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
-    return static_cast<size_t>(m + 1) * up(vec) + up(part) + up(scal);
+    return static_cast<size_t>(m + 1) * up(vec) + up(part) + up(scal) + up(fused);
 }
 
 template <typename T>
-KrylovRun<T>::KrylovRun(const DeviceTables &tb, uint64_t n, int m, char *ws, hipStream_t s)
-    : tb_(tb), n_(n), m_(m), s_(s) {
+KrylovRun<T>::KrylovRun(Hamiltonian &h, int blk, int rot, uint64_t n, int m, char *ws, hipStream_t s)
+    : h_(h), blk_(blk), rot_(rot), n_(n), m_(m), s_(s) {
     auto up = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
     vec_stride_ = up(static_cast<size_t>(n) * 2 * sizeof(T)) / (2 * sizeof(T));
     basis_ = reinterpret_cast<T *>(ws);
@@ -160,6 +163,8 @@ KrylovRun<T>::KrylovRun(const DeviceTables &tb, uint64_t n, int m, char *ws, hip
     beta2_ = alpha_ + 2 * (m + 2);            // m+2
     coef_ = beta2_ + (m + 2);                 // 2 (m+2)
     scratch_ = coef_ + 2 * (m + 2);           // 2 (m+2)
+    p += up(static_cast<size_t>(8 * (m + 4)) * sizeof(double));
+    fused_ = reinterpret_cast<double *>(p);   // 4 per tile
 }
 
 template <typename T>
@@ -179,8 +184,23 @@ template <typename T>
 void KrylovRun<T>::iterate(int j, int reorth) {
     T *vj = vec(j);
     T *w = vec(j + 1);
+    if (reorth == 0 && use_tiled<T>(h_.L)) {
+        // fused step: the apply epilogue forms w = H v_j - beta v_{j-1} and the sums for
+        // alpha_j and beta_j; one more pass normalises
+        LanczosFuse<T> lf;
+        lf.vprev = j > 0 ? vec(j - 1) : nullptr;
+        lf.vcur = vj;
+        lf.beta2_prev = beta2_ + j;
+        lf.partials = fused_;
+        if (timer_) timer_->begin(s_);
+        const int np = apply_block_lanczos<T>(h_, blk_, rot_, vj, w, lf, s_);
+        if (timer_) timer_->end(s_);
+        launch_lanczos_scalars(fused_, np, alpha_ + 2 * j, beta2_ + j + 1, s_);
+        launch_lanczos_update<T>(w, vj, alpha_ + 2 * j, beta2_ + j + 1, n_, s_);
+        return;
+    }
     if (timer_) timer_->begin(s_);
-    launch_apply_h<T>(tb_, vj, w, static_cast<uint32_t>(n_), 1, n_, s_);
+    apply_block<T>(h_, blk_, rot_, vj, w, 1, n_, s_);
     if (timer_) timer_->end(s_);
     launch_lanczos_orth1<T>(w, j > 0 ? vec(j - 1) : nullptr, vj, beta2_ + j, n_, partials_, n_part_, s_);
     launch_reduce_partials(partials_, n_part_, 2, alpha_ + 2 * j, s_);

@@ -46,7 +46,8 @@ template <typename T>
 class KrylovRun {
   public:
     // ws: device workspace of at least krylov_workspace_bytes(n, m, sizeof(T)) bytes
-    KrylovRun(const DeviceTables &tb, uint64_t n, int m, char *ws, hipStream_t s);
+    // rot: layout rotation of the vectors (0 = standard index order)
+    KrylovRun(Hamiltonian &h, int blk, int rot, uint64_t n, int m, char *ws, hipStream_t s);
     // out = e^{z H} v (out may equal v); accumulates into st
     void run(std::complex<double> z, const T *v, T *out, const syk_krylov_opts &o, syk_krylov_stats &st);
     double norm(const T *v);
@@ -59,13 +60,15 @@ class KrylovRun {
     T *vec(int j) { return basis_ + static_cast<size_t>(j) * vec_stride_ * 2; }
     void iterate(int j, int reorth);
 
-    const DeviceTables &tb_;
+    Hamiltonian &h_;
+    int blk_, rot_;
     uint64_t n_;
     int m_;
     hipStream_t s_;
     size_t vec_stride_ = 0;    // complex elements between basis vectors
     T *basis_ = nullptr;
     double *partials_ = nullptr, *alpha_ = nullptr, *beta2_ = nullptr, *coef_ = nullptr, *scratch_ = nullptr;
+    double *fused_ = nullptr;
     int n_part_ = 0;
     ApplyTimer *timer_ = nullptr;
 };

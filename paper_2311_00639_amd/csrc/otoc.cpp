@@ -29,17 +29,18 @@ size_t otoc_workspace_bytes(uint64_t n, int m, size_t elem_bytes) {
     return 4 * up(static_cast<size_t>(n) * 2 * elem_bytes) + krylov_workspace_bytes(n, m, elem_bytes);
 }
 
-// y = gamma_n block mapping `src` to the other block
+// y = gamma_n block mapping `src` to the other block, vectors in layout rotation `rot`
 template <typename T>
-void apply_gamma(int N, int n, int src, const T *x, T *y, uint64_t amps, hipStream_t s) {
+void apply_gamma(int N, int n, int src, int rot, const T *x, T *y, uint64_t amps, hipStream_t s) {
     if (n == N - 1) {
         // gamma_{N-1}^{UD} = -i (from D), gamma_{N-1}^{DU} = +i (from U)
         launch_majorana<T>(0u, 0u, 0, 0.0, src == 0 ? 1.0 : -1.0, x, y, amps, s);
     } else {
+        const int L = N / 2 - 1;
         uint32_t bx, bz;
         int bw;
         block_majorana(N, n, bx, bz, bw);
-        launch_majorana<T>(bx, bz, bw, 1.0, 0.0, x, y, amps, s);
+        launch_majorana<T>(rotr_bits(bx, rot, L), rotr_bits(bz, rot, L), bw, 1.0, 0.0, x, y, amps, s);
     }
 }
 
@@ -53,8 +54,12 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
     T *r4 = reinterpret_cast<T *>(ws + 2 * vb);
     T *tmp = reinterpret_cast<T *>(ws + 3 * vb);
     char *kws = ws + 4 * vb;
-    const DeviceTables *tb[2] = {&h.tables(0), &h.tables(1)};
-    KrylovRun<T> kr[2] = {KrylovRun<T>(*tb[0], n, o.krylov.m, kws, s), KrylovRun<T>(*tb[1], n, o.krylov.m, kws, s)};
+    // every vector of the chain lives in the planner's layout rotation; overlaps are
+    // invariant under the permutation
+    if (use_tiled<T>(h.L) && o.autotune) autotune<T>(h, l, tmp, s, false);     // l, tmp: scratch here
+    const int rot = !use_tiled<T>(h.L) ? 0 : (o.layout >= 0 ? o.layout : h.internal_rotation<T>(h.variant<T>()));
+    KrylovRun<T> kr[2] = {KrylovRun<T>(h, 0, rot, n, o.krylov.m, kws, s),
+                          KrylovRun<T>(h, 1, rot, n, o.krylov.m, kws, s)};
     ApplyTimer timer;
     if (o.profile) {
         kr[0].set_timer(&timer);
@@ -77,11 +82,11 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
             // psi: the A part into l, the B part into tmp (discarded), normalised over both
             T *pu = (A == 0) ? l : tmp;
             T *pd = (A == 0) ? tmp : l;
-            launch_haar_raw<T>(o.state_seed, v, h.L, pu, pd, kr[0].partials(), kr[0].n_part(), s);
+            launch_haar_raw<T>(o.state_seed, v, h.L, rot, pu, pd, kr[0].partials(), kr[0].n_part(), s);
             launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 1, kr[0].scratch(), s);
             launch_scale_pair<T>(pu, pd, n, kr[0].scratch(), s);
             prop(A, cd(-beta / 8.0, 0.0), l);                     // l = r0
-            apply_gamma<T>(h.N, j, A, l, r2, n, s);                // V_BA r0
+            apply_gamma<T>(h.N, j, A, rot, l, r2, n, s);                // V_BA r0
             prop(B, cd(-beta / 4.0, 0.0), r2);                     // r2
             double tprev = 0.0;
             for (int k = 0; k < nt; ++k) {
@@ -92,11 +97,11 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
                     prop(A, cd(0.0, -dt), l);
                 }
                 tprev = t;
-                apply_gamma<T>(h.N, i, B, r2, r4, n, s);           // W_AB r2
+                apply_gamma<T>(h.N, i, B, rot, r2, r4, n, s);           // W_AB r2
                 prop(A, cd(-beta / 4.0, t), r4);                   // r4
-                apply_gamma<T>(h.N, j, A, r4, tmp, n, s);          // V_BA r4
+                apply_gamma<T>(h.N, j, A, rot, r4, tmp, n, s);          // V_BA r4
                 prop(B, cd(-beta / 4.0, -t), tmp);                 // r6
-                apply_gamma<T>(h.N, i, B, tmp, r4, n, s);          // W_AB r6
+                apply_gamma<T>(h.N, i, B, rot, tmp, r4, n, s);          // W_AB r6
                 launch_dot_partials<T>(l, r4, n, kr[0].partials(), kr[0].n_part(), s);
                 launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 2, kr[0].scratch(), s);
                 SYK_HIP(hipMemcpyAsync(hd.data(), kr[0].scratch(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -117,7 +122,7 @@ template void otoc_run<float>(Hamiltonian &, int, int, double, const std::vector
                               std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t);
 template void otoc_run<double>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
                                std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t);
-template void apply_gamma<float>(int, int, int, const float *, float *, uint64_t, hipStream_t);
-template void apply_gamma<double>(int, int, int, const double *, double *, uint64_t, hipStream_t);
+template void apply_gamma<float>(int, int, int, int, const float *, float *, uint64_t, hipStream_t);
+template void apply_gamma<double>(int, int, int, int, const double *, double *, uint64_t, hipStream_t);
 
 }  // namespace syk

@@ -11,7 +11,7 @@ namespace syk {
 size_t otoc_workspace_bytes(uint64_t n, int m, size_t elem_bytes);
 
 template <typename T>
-void apply_gamma(int N, int n, int src, const T *x, T *y, uint64_t amps, hipStream_t s);
+void apply_gamma(int N, int n, int src, int rot, const T *x, T *y, uint64_t amps, hipStream_t s);
 
 // F[k] = mean over vectors of F_v(ts[k]) (complex); ws: otoc_workspace_bytes(2^L, m, sizeof(T))
 template <typename T>

@@ -3,6 +3,7 @@
 #include <map>
 #include <thread>
 
+#include "apply_plan.hpp"
 #include "internal.hpp"
 
 namespace syk {
@@ -62,15 +63,160 @@ const DeviceTables &Hamiltonian::tables(int blk) {
     return t;
 }
 
+template <>
+const std::vector<TiledVariant> &tiled_variants<float>() {
+    static const std::vector<TiledVariant> v = {{13, 3, 2, 1}, {12, 3, 2, 1}, {12, 2, 4, 3}, {11, 2, 2, 1}};
+    return v;
+}
+template <>
+const std::vector<TiledVariant> &tiled_variants<double>() {
+    static const std::vector<TiledVariant> v = {{12, 2, 2, 1}, {11, 2, 2, 1}, {11, 1, 4, 3}, {10, 1, 2, 1}};
+    return v;
+}
+template <>
+int default_variant<float>() { return 0; }
+template <>
+int default_variant<double>() { return 0; }
+
+template <typename T>
+const ApplyPlan &Hamiltonian::plan(int blk, int rot, int variant) {
+    int d = 0;
+    SYK_HIP(hipGetDevice(&d));
+    const int prec = sizeof(T) == 8 ? 1 : 0;
+    const TiledVariant &tv = tiled_variants<T>().at(variant);
+    std::lock_guard<std::mutex> g(dev_mu);
+    ApplyPlan &p = plans[std::make_tuple(blk, prec, d, rot, variant)];
+    if (p.grp_g) return p;
+    HostPlan hp = build_host_plan(block_terms[blk], L, tv.bt, tv.rb, tv.nbuf, tv.pf, rot, 2 * sizeof(T));
+    upload_plan(hp, tv.bt, tv.rb, p);
+    p.variant = variant;
+    return p;
+}
+template const ApplyPlan &Hamiltonian::plan<float>(int, int, int);
+template const ApplyPlan &Hamiltonian::plan<double>(int, int, int);
+
+template <typename T>
+int Hamiltonian::internal_rotation(int variant) {
+    if (!use_tiled<T>(L)) return 0;
+    const int prec = sizeof(T) == 8 ? 1 : 0;
+    std::lock_guard<std::mutex> g(dev_mu);
+    int &r = rotation[prec][variant];
+    if (r < 0) r = choose_rotation(block_terms[0], L, tiled_variants<T>().at(variant).bt);
+    return r;
+}
+template int Hamiltonian::internal_rotation<float>(int);
+template int Hamiltonian::internal_rotation<double>(int);
+
+template <typename T>
+int Hamiltonian::variant() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) d = 0;       // host-only queries: nothing tuned yet
+    std::lock_guard<std::mutex> g(dev_mu);
+    auto it = tuned.find({sizeof(T) == 8 ? 1 : 0, d});
+    return it == tuned.end() ? default_variant<T>() : it->second;
+}
+template int Hamiltonian::variant<float>();
+template int Hamiltonian::variant<double>();
+
+template <typename T>
+void apply_block(Hamiltonian &h, int blk, int rot, const T *x, T *y, int nvec, uint64_t ld, hipStream_t s) {
+    if (use_tiled<T>(h.L)) {
+        launch_apply_tiled<T>(h.plan<T>(blk, rot, h.variant<T>()), x, y, nvec, ld, s);
+    } else {
+        if (rot != 0) fail(SYK_EDEVICE, "rotated layouts are only planned for tiled blocks");
+        launch_apply_h<T>(h.tables(blk), x, y, 1u << h.L, nvec, ld, s);
+    }
+}
+template void apply_block<float>(Hamiltonian &, int, int, const float *, float *, int, uint64_t, hipStream_t);
+template void apply_block<double>(Hamiltonian &, int, int, const double *, double *, int, uint64_t, hipStream_t);
+
+template <typename T>
+int apply_block_lanczos(Hamiltonian &h, int blk, int rot, const T *x, T *y, const LanczosFuse<T> &lf,
+                        hipStream_t s) {
+    if (!use_tiled<T>(h.L)) fail(SYK_EDEVICE, "the fused Lanczos step needs a tiled block");
+    const ApplyPlan &pl = h.plan<T>(blk, rot, h.variant<T>());
+    if (pl.n_tiles > lanczos_partials_max(h.L)) fail(SYK_EDEVICE, "partials buffer too small");
+    launch_apply_tiled<T>(pl, x, y, 1, 1ULL << h.L, s, &lf);
+    return static_cast<int>(pl.n_tiles);
+}
+template int apply_block_lanczos<float>(Hamiltonian &, int, int, const float *, float *,
+                                        const LanczosFuse<float> &, hipStream_t);
+template int apply_block_lanczos<double>(Hamiltonian &, int, int, const double *, double *,
+                                         const LanczosFuse<double> &, hipStream_t);
+
+// Time every compiled variant of the tiled kernel on this Hamiltonian (block U, each in
+// its own planned layout) and keep the fastest for the current device.  x, y: scratch
+// device vectors of 2^L amplitudes.
+template <typename T>
+int autotune(Hamiltonian &h, T *x, T *y, hipStream_t s, bool force, std::vector<float> *times) {
+    if (!use_tiled<T>(h.L)) return -1;
+    int dev = 0;
+    SYK_HIP(hipGetDevice(&dev));
+    if (!force) {
+        std::lock_guard<std::mutex> g(h.dev_mu);
+        auto it = h.tuned.find({sizeof(T) == 8 ? 1 : 0, dev});
+        if (it != h.tuned.end()) return it->second;
+    }
+    const auto &vars = tiled_variants<T>();
+    const uint64_t n = 1ULL << h.L;
+    const int np = reduction_blocks(n);
+    double *part = nullptr;
+    SYK_HIP(hipMalloc(reinterpret_cast<void **>(&part), (np + 1) * sizeof(double)));
+    hipEvent_t e0, e1;
+    SYK_HIP(hipEventCreate(&e0));
+    SYK_HIP(hipEventCreate(&e1));
+    int best = default_variant<T>();
+    float best_ms = 1e30f;
+    if (times) times->assign(vars.size(), -1.0f);
+    try {
+        launch_haar_raw<T>(1, 0, h.L - 1, 0, x, x + n, part, np, s);     // any finite data
+        for (int v = 0; v < static_cast<int>(vars.size()); ++v) {
+            if (vars[v].bt + 3 > h.L) continue;                          // needs >= 8 tiles
+            const ApplyPlan &pl = h.plan<T>(0, h.internal_rotation<T>(v), v);
+            launch_apply_tiled<T>(pl, x, y, 1, n, s);                    // warm-up
+            SYK_HIP(hipEventRecord(e0, s));
+            for (int k = 0; k < 3; ++k) launch_apply_tiled<T>(pl, x, y, 1, n, s);
+            SYK_HIP(hipEventRecord(e1, s));
+            SYK_HIP(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            SYK_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (times) (*times)[v] = ms / 3.0f;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = v;
+            }
+        }
+    } catch (...) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        hipFree(part);
+        throw;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(part);
+    std::lock_guard<std::mutex> g(h.dev_mu);
+    h.tuned[{sizeof(T) == 8 ? 1 : 0, dev}] = best;
+    return best;
+}
+template int autotune<float>(Hamiltonian &, float *, float *, hipStream_t, bool, std::vector<float> *);
+template int autotune<double>(Hamiltonian &, double *, double *, hipStream_t, bool, std::vector<float> *);
+
 Hamiltonian::~Hamiltonian() {
     int cur = 0;
     bool have = hipGetDevice(&cur) == hipSuccess;
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
         for (size_t d = 0; d < dev[b].size(); ++d)
             if (dev[b][d].x) {
                 if (have) hipSetDevice(static_cast<int>(d));
                 free_tables(dev[b][d]);
             }
+    }
+    for (auto &kv : plans)
+        if (kv.second.grp_g) {
+            if (have) hipSetDevice(std::get<2>(kv.first));
+            free_plan(kv.second);
+        }
     if (have) hipSetDevice(cur);
 }
 

@@ -137,6 +137,42 @@ def test_apply_h_sampled_rows_N56_c64():
     assert np.all(np.abs(y - yref) <= K * U24 * mag)
 
 
+@pytest.mark.parametrize("N,dt,blk", [(36, syk.C128, 0), (38, syk.C128, 0), (38, syk.C128, 1), (38, syk.C64, 0),
+                                       (40, syk.C64, 0), (40, syk.C64, 1), (44, syk.C128, 1)])
+def test_apply_h_tiled_smallest_sizes(N, dt, blk):
+    """Blocks on both sides of the gather/tiled switch (the tiled kernel serves 2^5 tiles
+    and up: N >= 38 in complex128, N >= 40 in complex64), sampled rows."""
+    y, yref, mag, K = _sampled_rows_check(N, 3, N + 1, dt, blk, nrows=6000)
+    if dt == syk.C128:
+        assert np.all(np.abs(y - yref) <= K * 2.0 ** -52 * mag)
+    else:
+        assert np.all(np.abs(y - yref) <= K * U24 * mag)
+
+
+def test_apply_h_tiled_many_vectors_padded():
+    """nvec = 3 vectors at a padded leading dimension through the tiled kernel (N = 40)."""
+    N, k, seed = 40, 4, 12
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    n = 1 << (N // 2 - 1)
+    nvec, ld = 3, n + 1000
+    X = torch.zeros(nvec, ld, dtype=torch.complex64, device="cuda")
+    for v in range(nvec):
+        X[v, :n] = dev(inputs.complex_vector(n, 30 + v)[0], torch.complex64)
+    X[:, n:] = 5.0
+    Y = torch.full_like(X, 2.0)
+    syk.apply_H(h, 0, X, Y, nvec=nvec, ld=ld)
+    rows = inputs.row_sample(n, 3000, 9)
+    terms = matfree.block_terms(N, subs, J, 0)
+    Xh = host(X)
+    Yh = host(Y)
+    for v in range(nvec):
+        xr = Xh[v, :n]
+        yref = matfree.apply_rows(terms, lambda idx: xr[idx.astype(np.int64)], rows)
+        assert rel(Yh[v, rows.astype(np.int64)], yref) <= 4e-6
+    assert np.all(Yh[:, n:] == 2.0)
+
+
 def test_apply_h_hermitian_N40():
     """<u, H v> = conj <v, H u> for Haar-like u, v (exact up to rounding)."""
     h = syk.create_hamiltonian(40, 4, 4, 40)
@@ -236,6 +272,27 @@ def test_krylov_in_place_and_unitary():
     assert (torch.linalg.vector_norm(a - w) / n0).item() < 1e-10
 
 
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_krylov_fused_step_matches_full_reorth_N40(dt):
+    """N = 40 runs the fused tiled Lanczos step (reorth = 0); full re-orthogonalisation
+    (reorth = 2, separate kernels) must give the same propagator to the tolerance."""
+    h = syk.create_hamiltonian(40, 4, 4, 40)
+    n = 1 << 19
+    vd = dev(inputs.complex_vector(n, 21)[0], cdt(dt))
+    tol = 1e-10 if dt == syk.C128 else 2e-6
+    for z in (-2.5j, 1.5j - 0.6, -9.0j):
+        a = torch.empty_like(vd)
+        b = torch.empty_like(vd)
+        sa = syk.krylov_expm(h, 1, z, vd, a, m=40, reorth=0)
+        sb = syk.krylov_expm(h, 1, z, vd, b, m=40, reorth=2)
+        err = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+        assert err <= tol, (z, err, sa, sb)
+    # unitary evolution keeps the norm
+    syk.krylov_expm(h, 0, -7.0j, vd, a, m=40)
+    r = (torch.linalg.vector_norm(a) / torch.linalg.vector_norm(vd)).item()
+    assert abs(r - 1) <= (1e-11 if dt == syk.C128 else 2e-6)
+
+
 def test_krylov_single_term_breakdown_N48():
     """H = (J/4) P with P^2 = 1: e^{-iHt} v = cos(Jt/4) v - i sin(Jt/4) P v exactly; the
     Krylov space has dimension 2 (breakdown)."""
@@ -315,6 +372,23 @@ def test_otoc_single_term_closed_forms_large_N(N, dt):
     assert np.abs(raw + 0.25).max() <= tol
     _, nrm, _, _ = syk.otoc(h, others[0], others[1], 4.0, ts, state_seed=3, dtype=dt, m=8)
     assert np.abs(nrm - 1).max() <= 2 * tol
+
+
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_otoc_rotated_layout_matches_standard_N40(dt):
+    """The planner's rotated vector layout gives the same OTOC as the standard layout
+    (whose apply_H, Haar and Majorana kernels are checked against the oracle above)."""
+    h = syk.create_hamiltonian(40, 4, 4, 41)
+    plan = syk.plan_describe(h, 0, dt)
+    assert plan["tiled"] == 1
+    ts = [0.0, 0.5, 1.5]
+    a = syk.otoc(h, 39, 38, 3.0, ts, state_seed=2, dtype=dt, m=30, layout=-1)
+    b = syk.otoc(h, 39, 38, 3.0, ts, state_seed=2, dtype=dt, m=30, layout=0)
+    c = syk.otoc(h, 39, 38, 3.0, ts, state_seed=2, dtype=dt, m=30, layout=7)
+    tol = 1e-9 if dt == syk.C128 else 2e-5
+    for other in (b, c):
+        assert np.abs(a[0] - other[0]).max() <= tol * max(1.0, np.abs(a[0]).max())
+        assert np.abs(a[1] - other[1]).max() <= tol * 10
 
 
 def test_otoc_beta0_t0_minus_quarter_N40():

@@ -112,3 +112,25 @@ def test_sigma_and_sumJ2_consistent():
     inf = h.info()
     T = h.terms()
     assert abs(inf["sum_J2"] - float(np.sum(T["J"] ** 2))) < 1e-14
+
+
+@pytest.mark.parametrize("N,k,dt", [(40, 4, syk.C64), (48, 4, syk.C128), (56, 4, syk.C64), (64, 8, syk.C64)])
+def test_plan_describe(N, k, dt):
+    """Planner invariants (host-only): bijective tile map and complete grouping are checked
+    inside the call; the planner's layout groups no worse than the standard order."""
+    h = syk.create_hamiltonian(N, 4, k, N)
+    auto = syk.plan_describe(h, 0, dt, -1)
+    std = syk.plan_describe(h, 0, dt, 0)
+    assert auto["tiled"] == 1 and std["tiled"] == 1
+    L = N // 2 - 1
+    assert auto["n_tiles"] == 1 << (L - auto["tile_bits"]) and 0 <= auto["rot"] < L
+    assert 1 <= auto["classes8"] <= auto["classes5"] <= auto["n_groups"] <= h.info()["K"]
+    cost = lambda d: d["n_groups"] + 2 * d["classes5"] + 0.5 * d["classes8"]
+    assert cost(auto) <= cost(std) + 1e-9
+    # the D block shares the x masks: same grouping
+    assert syk.plan_describe(h, 1, dt, auto["rot"])["n_groups"] == auto["n_groups"]
+
+
+def test_plan_describe_small_block_not_tiled():
+    h = syk.create_hamiltonian(16, 4, 4, 1)
+    assert syk.plan_describe(h, 0, syk.C64)["tiled"] == 0
