@@ -4,13 +4,20 @@ Workload (mixed precision at scale): N = 56 Majoranas (parity blocks of 2^27 amp
 q = 4, k = 4 (K = 224 terms), one disorder realisation (seed 56), complex64 state
 vectors with double Lanczos reductions and tridiagonal exponential, Krylov dimension 60,
 one Haar state (state_seed 5600), W = chi_55, V = chi_54, beta in {5, 10, 20},
-t = 0, 0.25, ..., 20 (81 points).  One step is one OTOC realisation: the three beta
-curves, both parity-block chains, every t point.
+t = 0, 0.25, ..., 20 (81 points).
 
-Printed: one JSON line.  value = OTOC realisations per hour; roofline of the dominant
-kernel (apply_H) from HIP-event timings of every apply_H launch in the timed region;
-cpu_baseline = the oracle's matrix-free row evaluation timed on a bounded sample and
-scaled by the term-amplitudes one realisation needs.
+A step is one complete OTOC curve (one beta, both parity-block chains, all 81 t points);
+steps cycle beta through 10, 5, 20, and a realisation is the three curves, so
+value = realisations per hour = 3600 * steps / (3 * elapsed) (exact when steps is a
+multiple of 3; a single step measures the middle-cost beta).
+
+Printed: one JSON line with the roofline of the dominant kernel (apply_H), taken from
+HIP-event timings of every apply_H launch in the timed region, and cpu_baseline = the
+oracle's matrix-free row evaluation timed on a bounded sample, scaled by the
+term-amplitudes one realisation needs.
+
+--pmc-sample runs a short chain (one beta, t = 0, 0.25, 0.5) in the identical launch
+configuration plus a 1 GiB device copy, for hardware-counter passes.
 """
 import argparse
 import json
@@ -22,10 +29,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N, K_SPARSITY, SEED, STATE_SEED = 56, 4, 56, 5600
-BETAS = (5.0, 10.0, 20.0)
+BETAS = (10.0, 5.0, 20.0)
 M_KRYLOV = 60
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# HBM traffic of one apply_H launch of this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
+# plain device copy of known size (profiles/apply_h_tiled_N56_k4_c64_traffic.txt).  Valid
+# only for the kernel revision it was measured on.
+TRAFFIC = {"kernel_rev": "tiled-dma-5", "fetch_bytes": 47161464021, "write_bytes": 1074283160}
 
 
 def t_grid():
@@ -41,7 +54,7 @@ def cpu_baseline(term_amps_per_realisation: float, seconds_target: float = 12.0)
     terms = matfree.block_terms(N, subs, J, 0)
     n = 1 << (N // 2 - 1)
     rng = np.random.default_rng(1)
-    x = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
+    x = (rng.standard_normal(n, dtype=np.float32) + 1j * rng.standard_normal(n, dtype=np.float32)).astype(np.complex64)
     xat = lambda idx: x[idx.astype(np.int64)].astype(np.complex128)
     rows_per_call = 1 << 16
     done = 0
@@ -65,45 +78,67 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-sample", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: the sparse-SYK OTOC path here is single-GPU "
-              "(realisations shard across GPUs as independent jobs); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: realisations of the sparse-SYK OTOC are independent jobs "
+              "and shard across GPUs with no communication; run one process per GPU with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2311_00639_amd as syk
 
     torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
     h = syk.create_hamiltonian(N, 4, K_SPARSITY, SEED)
     info = h.info()
+    # one-time setup outside the timed region: plans for every kernel variant, autotuning
+    variant, variant_ms = syk.autotune(h, syk.C64, stream=stream)
+    plan = syk.plan_describe(h, 0, syk.C64, -1)
+
+    if args.pmc_sample:
+        raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, BETAS[0], [0.0, 0.25, 0.5], state_seed=STATE_SEED,
+                                    dtype=syk.C64, m=M_KRYLOV, profile=True, stream=stream)
+        x = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+        x.zero_()
+        y = x.clone()                     # calibration: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_sample": True, "apply_launches": st["apply_launches"],
+                          "apply_ms_avg": st["apply_ms"] / st["apply_launches"], "copy_bytes": x.numel() * 8,
+                          "variant": variant, "plan": plan}), flush=True)
+        del x, y
+        return
+
     ts = t_grid()
-    stream = torch.cuda.current_stream()
 
-    def step(profile):
-        out = []
-        for beta in BETAS:
-            raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, beta, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64,
-                                        m=M_KRYLOV, profile=profile, stream=stream)
-            out.append((raw, nrm, im, st))
-        return out
+    def curve(beta, profile):
+        t_start = time.perf_counter()
 
-    for _ in range(args.warmup):
-        step(False)
+        def progress(done, total):
+            if done % 9 == 0 or done == total:
+                print(f"[bench] beta={beta:g}: {done}/{total} chain t-points, {time.perf_counter() - t_start:.0f} s",
+                      file=sys.stderr, flush=True)
+        return syk.otoc(h, N - 1, N - 2, beta, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64, m=M_KRYLOV,
+                        profile=profile, progress=progress, stream=stream)
+
+    for w in range(args.warmup):
+        curve(BETAS[w % 3], False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
-    for _ in range(args.steps):
-        results.append(step(True))
+    for s in range(args.steps):
+        beta = BETAS[s % 3]
+        results.append((beta, curve(beta, True)))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
-    apply_ms = sum(st["apply_ms"] for r in results for (_, _, _, st) in r)
-    launches = sum(st["apply_launches"] for r in results for (_, _, _, st) in r)
-    matvecs = sum(st["matvecs"] for r in results for (_, _, _, st) in r)
+    stats = [r[1][3] for r in results]
+    apply_ms = sum(st["apply_ms"] for st in stats)
+    launches = sum(st["apply_launches"] for st in stats)
+    matvecs = sum(st["matvecs"] for st in stats)
     K = info["K"]
     n = info["block_dim"]
     avg_s = apply_ms / 1e3 / max(launches, 1)
@@ -111,8 +146,12 @@ def main():
     flops = 4.0 * term_amps                   # complex amplitude times real coefficient: 2 FMA
     alg_bytes = 2.0 * n * 8                   # read x once, write y once (complex64)
     achieved_tflops = flops / avg_s / 1e12
-    value = args.steps * 3600.0 / elapsed
-    term_amps_per_real = matvecs / args.steps * term_amps
+    value = 3600.0 * args.steps / (3.0 * elapsed)
+    term_amps_per_real = 3.0 * matvecs / args.steps * term_amps
+    lib_rev = syk.kernel_revision()
+    traffic = None
+    if TRAFFIC["fetch_bytes"] and TRAFFIC["kernel_rev"] == lib_rev:
+        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
     rec = {
         "metric": "apply_H term-amps/s & % HBM peak; OTOC realisations/h N=56 k=4; p50/p99",
@@ -129,17 +168,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sparse SYK OTOC realisation: N=56, q=4, k=4 (K=224), complex64 states, "
                                "double Lanczos reductions, Krylov dim 60, beta in {5,10,20}, t=0:0.25:20, "
-                               "1 Haar state, W=chi_55, V=chi_54",
+                               "1 Haar state, W=chi_55, V=chi_54; one step = one beta curve",
                    "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "betas": list(BETAS), "nt": len(ts),
-                   "parallelism": "single GPU"},
+                   "betas_timed": [b for b, _ in results], "parallelism": "single GPU"},
         "apply_H_term_amps_per_s": term_amps / avg_s,
         "apply_H_ms": avg_s * 1e3,
         "apply_H_algorithmic_hbm_frac": alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS,
-        "matvecs_per_realisation": matvecs / args.steps,
+        "matvecs_per_curve": matvecs / args.steps,
+        "kernel": {"revision": lib_rev, "variant": variant, "variant_ms": variant_ms, "plan": plan},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "apply_H", "launches_timed": launches},
-        "otoc_F_norm_t1": {str(b): float(r[1][4]) for b, r in zip(BETAS, results[-1])},
+                     "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "apply_h_tiled", "launches_timed": launches},
+        "otoc_F_norm": {str(b): [float(r[1][i]) for i in (4, 20, 40, 80)] for b, r in results},
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(term_amps_per_real)

@@ -157,6 +157,10 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
                            syk_krylov_stats *stats, void *stream);
 
 /* ---------------------------------------------------------------- OTOC */
+/* Called on the calling thread after each t point of each vector and block chain:
+ * done = chain steps completed so far, total = nvec * 2 * nt. */
+typedef void (*syk_progress_fn)(void *ctx, int done, int total);
+
 typedef struct {
     int nvec;              /* Haar vectors averaged (>= 1) */
     uint64_t state_seed;   /* vector v uses syk_haar_state(N, state_seed, v, ...) */
@@ -167,6 +171,8 @@ typedef struct {
                               syk_plan_describe); r >= 0: bit rotation r (0 = standard order) */
     int autotune;          /* 1: before the first run of this handle/precision/device, time the
                               tiled apply_H variants and keep the fastest (syk_autotune) */
+    syk_progress_fn progress;   /* optional (NULL = none) */
+    void *progress_ctx;
 } syk_otoc_opts;
 
 typedef struct {
@@ -229,6 +235,10 @@ syk_status syk_autotune(const syk_ham *h, syk_dtype dt, int *variant, float *ms,
 
 /* Release the library's cached device workspaces on the current device. */
 syk_status syk_release_workspace(void);
+
+/* Identifier of the apply_H kernel revision built into this library (changes whenever the
+ * kernel's memory behaviour may change; hardware-counter figures are tied to it). */
+const char *syk_kernel_revision(void);
 
 const char *syk_status_string(syk_status s);
 const char *syk_last_error(void);    /* thread-local; "" if none */

@@ -21,6 +21,7 @@ from ._lib import (  # noqa: F401
     autotune,
     create_hamiltonian,
     haar_state,
+    kernel_revision,
     krylov_expm,
     library_path,
     otoc,

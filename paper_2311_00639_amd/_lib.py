@@ -42,9 +42,13 @@ class KrylovStats(ct.Structure):
     _fields_ = [("substeps", ct.c_int), ("matvecs", ct.c_int), ("breakdown", ct.c_int), ("err_est", ct.c_double)]
 
 
+PROGRESS_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_int, ct.c_int)
+
+
 class OtocOpts(ct.Structure):
     _fields_ = [("nvec", ct.c_int), ("state_seed", ct.c_uint64), ("dtype", ct.c_int), ("krylov", KrylovOpts),
-                ("profile", ct.c_int), ("layout", ct.c_int), ("autotune", ct.c_int)]
+                ("profile", ct.c_int), ("layout", ct.c_int), ("autotune", ct.c_int),
+                ("progress", PROGRESS_FN), ("progress_ctx", ct.c_void_p)]
 
 
 class PlanDesc(ct.Structure):
@@ -84,6 +88,8 @@ _lib.syk_status_string.argtypes = [ct.c_int]
 _lib.syk_status_string.restype = ct.c_char_p
 _lib.syk_last_error.argtypes = []
 _lib.syk_last_error.restype = ct.c_char_p
+_lib.syk_kernel_revision.argtypes = []
+_lib.syk_kernel_revision.restype = ct.c_char_p
 _lib.syk_krylov_default_opts.argtypes = [ct.c_int, ct.POINTER(KrylovOpts)]
 _lib.syk_krylov_default_opts.restype = None
 
@@ -214,9 +220,10 @@ def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None,
 
 def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_seed: int = 0, dtype: int = C128,
          m: int = None, tol: float = None, reorth: int = None, profile: bool = False, layout: int = -1,
-         autotune: bool = True, stream=None):
+         autotune: bool = True, progress=None, stream=None):
     """Regularised OTOC (Eq. (2)) by the random-state estimator.  Returns
-    (F_raw, F_norm, F_imag, stats) with numpy float64 arrays."""
+    (F_raw, F_norm, F_imag, stats) with numpy float64 arrays.  progress(done, total) is
+    called after each t point of each chain."""
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
     nt = t.size
     o = OtocOpts()
@@ -227,6 +234,10 @@ def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_
     o.profile = 1 if profile else 0
     o.layout = layout
     o.autotune = 1 if autotune else 0
+    cb = None
+    if progress is not None:
+        cb = PROGRESS_FN(lambda ctx, done, total: progress(done, total))
+        o.progress = cb
     if m is not None:
         o.krylov.m = m
     if tol is not None:
@@ -276,6 +287,10 @@ def autotune(ham: Hamiltonian, dtype: int, stream=None):
     ms = (ct.c_float * 16)()
     _check(_lib.syk_autotune(ham.handle, dtype, ct.byref(v), ms, 16, _stream(stream)))
     return v.value, [round(float(t), 4) for t in ms if t != -1.0]
+
+
+def kernel_revision() -> str:
+    return _lib.syk_kernel_revision().decode()
 
 
 def release_workspace():

@@ -391,4 +391,6 @@ const char *syk_status_string(syk_status s) {
 
 const char *syk_last_error(void) { return g_last_error.c_str(); }
 
+const char *syk_kernel_revision(void) { return "tiled-dma-5"; }
+
 }  // extern "C"

@@ -76,6 +76,8 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
         st.substeps += ks.substeps;
         st.max_err_est = std::max(st.max_err_est, ks.err_est);
     };
+    int done = 0;
+    const int total = o.nvec * 2 * nt;
     for (int v = 0; v < o.nvec; ++v) {
         for (int A = 0; A < 2; ++A) {
             const int B = 1 - A;
@@ -108,6 +110,8 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
                 SYK_HIP(hipStreamSynchronize(s));
                 if (!std::isfinite(hd[0]) || !std::isfinite(hd[1])) fail(SYK_ENUMERIC, "non-finite OTOC overlap");
                 F[k] += 0.25 * cd(hd[0], hd[1]);
+                ++done;
+                if (o.progress) o.progress(o.progress_ctx, done, total);
             }
         }
     }
