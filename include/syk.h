@@ -48,7 +48,8 @@ typedef enum {
     SYK_EDEVICE = 4,       /* a HIP runtime call failed, or no GPU */
     SYK_ENOTCONV = 5,      /* Krylov step control could not meet the tolerance */
     SYK_ENUMERIC = 6,      /* NaN/Inf met in a reduction */
-    SYK_ECANCELLED = 7     /* request cancelled (engine) */
+    SYK_ECANCELLED = 7,    /* request cancelled (engine) */
+    SYK_EAGAIN = 8         /* engine: no finished request within the wait */
 } syk_status;
 
 typedef enum { SYK_C64 = 0, SYK_C128 = 1 } syk_dtype;
@@ -196,6 +197,89 @@ typedef struct {
 syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t, int nt,
                     const syk_otoc_opts *o, double *F_raw, double *F_norm, double *F_imag,
                     syk_otoc_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------- request engine */
+/* Serving engine: OTOC requests of mixed N, k and seed (one disorder realisation each,
+ * the quantity of syk_otoc) taken as they arrive, with continuous batching: a request is
+ * admitted as soon as a slot is free and its device footprint (Krylov basis, chain
+ * vectors, term tables and plans) fits in the remaining budget, so requests arriving
+ * while others run join them on the device.  Each slot is a host worker thread with its
+ * own HIP stream on the device current at syk_engine_create; kernels of different
+ * requests overlap on the GPU.  Admission is first-fit in arrival order: a request that
+ * does not fit may be overtaken by smaller ones at most max_bypass times, after which
+ * nothing else is admitted until it fits.  A request asking for more memory than the
+ * budget runs with a lower Krylov dimension (down to its m_min); the dimension used is
+ * reported.  Each result is computed with the same kernels and arithmetic as the same
+ * request run alone through syk_otoc (autotune = 0, planner layout), so it does not depend
+ * on what else is admitted.
+ * The engine owns the Krylov state, tables and workspaces of admitted requests until they
+ * finish or are cancelled; the caller owns the host arrays it passes (the t grid is copied
+ * at submit). */
+typedef struct syk_engine syk_engine;
+
+typedef struct {
+    uint64_t budget_bytes; /* device memory for admitted requests; 0 = 85% of free memory */
+    int max_active;        /* requests running at once (one stream each); 0 = 4 */
+    int max_bypass;        /* times a waiting request may be overtaken; < 0 = 8 */
+} syk_engine_opts;
+
+typedef struct {
+    int N;                 /* Majoranas of this request's realisation */
+    double k;              /* sparsity; K = round(k N) */
+    uint64_t seed;         /* realisation seed (syk_create_hamiltonian) */
+    int i, j;              /* W = chi_i, V = chi_j */
+    double beta;
+    const double *t;       /* host, nt non-decreasing times >= 0; copied at submit */
+    int nt;
+    int nvec;              /* Haar vectors (>= 1) */
+    uint64_t state_seed;
+    syk_dtype dtype;
+    int m;                 /* Krylov dimension wanted (0 = 30) */
+    int m_min;             /* lowest dimension accepted under memory pressure (0 = min(m, 8)) */
+    double tol;            /* per-propagation tolerance (<= 0: the dtype's default) */
+} syk_request;
+
+typedef struct {
+    uint64_t id;
+    syk_status status;     /* SYK_OK, SYK_ECANCELLED or the error of the run */
+    int nt;                /* entries written to each output array */
+    int m_used;            /* Krylov dimension the request ran with */
+    uint64_t footprint_bytes;
+    double t_submit, t_start, t_end;   /* seconds since syk_engine_create */
+    syk_otoc_stats stats;
+} syk_result_info;
+
+typedef struct {
+    long long submitted, completed, failed, cancelled;
+    int queued, active;
+    uint64_t budget_bytes, bytes_in_use, peak_bytes;
+    double p50_latency_s, p99_latency_s;   /* submit-to-finish over requests finished OK */
+    double busy_seconds;                   /* time with at least one request running */
+} syk_engine_stats;
+
+/* Start the engine on the current HIP device.  Errors: EINVAL, EDEVICE, ENOMEM. */
+syk_status syk_engine_create(const syk_engine_opts *o, syk_engine **out);
+
+/* Queue one request; *id receives its identifier (> 0).  Errors: EINVAL (arguments as in
+ * syk_create_hamiltonian and syk_otoc), ENOMEM (the footprint at m_min exceeds the
+ * budget: it could never be admitted). */
+syk_status syk_engine_submit(syk_engine *e, const syk_request *r, uint64_t *id);
+
+/* Take one finished request, waiting up to wait_ms milliseconds (0 = do not wait, < 0 =
+ * wait until one finishes or nothing is queued or running).  F_raw, F_norm, F_imag: host
+ * arrays of cap doubles (any may be NULL), filled as by syk_otoc.  Returns SYK_EAGAIN if
+ * none finished in time, SYK_EINVAL if cap is below the request's nt (the result is kept). */
+syk_status syk_engine_poll(syk_engine *e, int wait_ms, syk_result_info *info, double *F_raw, double *F_norm,
+                           double *F_imag, int cap);
+
+/* Cancel a queued or running request; it finishes with SYK_ECANCELLED (a running one at
+ * its next t point).  Errors: EINVAL (unknown or already finished id). */
+syk_status syk_engine_cancel(syk_engine *e, uint64_t id);
+
+syk_status syk_engine_get_stats(syk_engine *e, syk_engine_stats *st);
+
+/* Cancel everything, join the workers, free all device memory; NULL is a no-op. */
+syk_status syk_engine_destroy(syk_engine *e);
 
 /* ---------------------------------------------------------------- helpers */
 

@@ -2,7 +2,7 @@
 
 H = sum over kept 4-subsets i<j<k<l of J_ijkl chi_i chi_j chi_k chi_l, with Gaussian
 J of zero mean.  The paper's sparsity parameter is k = (p/N) C(N,4), so the mean
-number of kept terms is kN.  Readings adopted (listed in the design doc):
+number of kept terms is kN.  Readings adopted:
 
 * exactly K = round(kN) distinct 4-subsets are kept, drawn uniformly, and the
   keep-probability entering the variance is p = K / C(N,4);

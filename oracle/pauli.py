@@ -6,7 +6,7 @@ acts on qubit q, which is bit q of the basis index, and p is the power of i of a
 overall phase.  Products are taken qubit by qubit with the single-qubit table
 sigma_a sigma_b = delta_ab I + i eps_abc sigma_c.
 
-Readings adopted (listed in the design doc):
+Readings adopted:
 * sigma_y = [[0, -i], [i, 0]] (the textbook sign; the supplement prints the other
   sign, which only relabels J signs and leaves the ensemble unchanged);
 * block Majoranas on L = N/2 - 1 qubits, from the compact form of Eq. (S1):

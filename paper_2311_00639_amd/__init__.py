@@ -6,11 +6,15 @@ streams by their HIP handle) and raises on non-OK status codes.  There is no
 Python or CPU fallback: if the library is missing, importing the binding raises.
 
 Names follow the C ABI in ``include/syk.h``: create_hamiltonian, apply_H,
-haar_state, apply_majorana, krylov_expm, otoc, workspace_bytes, tridiag_expm.
+haar_state, apply_majorana, krylov_expm, otoc, workspace_bytes, tridiag_expm, and the
+request engine (Engine: syk_engine_create / submit / poll / cancel / get_stats / destroy).
 """
 from ._lib import (  # noqa: F401
     C64,
     C128,
+    ECANCELLED,
+    EAGAIN,
+    Engine,
     BLOCK_U,
     BLOCK_D,
     SykError,

@@ -11,7 +11,8 @@ C64, C128 = 0, 1
 BLOCK_U, BLOCK_D = 0, 1
 
 STATUS = {0: "SYK_OK", 1: "SYK_EINVAL", 2: "SYK_EUNSUPPORTED", 3: "SYK_ENOMEM", 4: "SYK_EDEVICE",
-          5: "SYK_ENOTCONV", 6: "SYK_ENUMERIC", 7: "SYK_ECANCELLED"}
+          5: "SYK_ENOTCONV", 6: "SYK_ENUMERIC", 7: "SYK_ECANCELLED", 8: "SYK_EAGAIN"}
+EAGAIN, ECANCELLED = 8, 7
 
 
 class SykError(RuntimeError):
@@ -62,6 +63,30 @@ class OtocStats(ct.Structure):
                 ("max_err_est", ct.c_double), ("apply_ms", ct.c_double), ("apply_launches", ct.c_longlong)]
 
 
+class EngineOpts(ct.Structure):
+    _fields_ = [("budget_bytes", ct.c_uint64), ("max_active", ct.c_int), ("max_bypass", ct.c_int)]
+
+
+class Request(ct.Structure):
+    _fields_ = [("N", ct.c_int), ("k", ct.c_double), ("seed", ct.c_uint64), ("i", ct.c_int), ("j", ct.c_int),
+                ("beta", ct.c_double), ("t", ct.POINTER(ct.c_double)), ("nt", ct.c_int), ("nvec", ct.c_int),
+                ("state_seed", ct.c_uint64), ("dtype", ct.c_int), ("m", ct.c_int), ("m_min", ct.c_int),
+                ("tol", ct.c_double)]
+
+
+class ResultInfo(ct.Structure):
+    _fields_ = [("id", ct.c_uint64), ("status", ct.c_int), ("nt", ct.c_int), ("m_used", ct.c_int),
+                ("footprint_bytes", ct.c_uint64), ("t_submit", ct.c_double), ("t_start", ct.c_double),
+                ("t_end", ct.c_double), ("stats", OtocStats)]
+
+
+class EngineStats(ct.Structure):
+    _fields_ = [("submitted", ct.c_longlong), ("completed", ct.c_longlong), ("failed", ct.c_longlong),
+                ("cancelled", ct.c_longlong), ("queued", ct.c_int), ("active", ct.c_int),
+                ("budget_bytes", ct.c_uint64), ("bytes_in_use", ct.c_uint64), ("peak_bytes", ct.c_uint64),
+                ("p50_latency_s", ct.c_double), ("p99_latency_s", ct.c_double), ("busy_seconds", ct.c_double)]
+
+
 _vp, _u64, _i, _d = ct.c_void_p, ct.c_uint64, ct.c_int, ct.c_double
 _dp = ct.POINTER(ct.c_double)
 _SIGS = {
@@ -79,6 +104,12 @@ _SIGS = {
     "syk_release_workspace": [],
     "syk_plan_describe": [_vp, _i, _i, _i, ct.POINTER(PlanDesc)],
     "syk_autotune": [_vp, _i, ct.POINTER(_i), ct.POINTER(ct.c_float), _i, _vp],
+    "syk_engine_create": [ct.POINTER(EngineOpts), ct.POINTER(_vp)],
+    "syk_engine_submit": [_vp, ct.POINTER(Request), ct.POINTER(_u64)],
+    "syk_engine_poll": [_vp, _i, ct.POINTER(ResultInfo), _dp, _dp, _dp, _i],
+    "syk_engine_cancel": [_vp, _u64],
+    "syk_engine_get_stats": [_vp, ct.POINTER(EngineStats)],
+    "syk_engine_destroy": [_vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -295,3 +326,61 @@ def kernel_revision() -> str:
 
 def release_workspace():
     _check(_lib.syk_release_workspace())
+
+
+class Engine:
+    """Request engine (syk_engine_*): continuous batching of OTOC requests on the current
+    device.  submit() returns an id; poll() returns finished results as dicts."""
+
+    def __init__(self, budget_bytes: int = 0, max_active: int = 4, max_bypass: int = 8):
+        o = EngineOpts(budget_bytes, max_active, max_bypass)
+        h = ct.c_void_p()
+        _check(_lib.syk_engine_create(ct.byref(o), ct.byref(h)))
+        self._h = h
+        self._nt = {}
+
+    def submit(self, N: int, k: float, seed: int, beta: float, t, i: int = None, j: int = None, nvec: int = 1,
+               state_seed: int = 0, dtype: int = C64, m: int = 30, m_min: int = 0, tol: float = 0.0) -> int:
+        t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+        r = Request(N, float(k), seed, N - 1 if i is None else i, N - 2 if j is None else j, float(beta),
+                    t.ctypes.data_as(_dp), t.size, nvec, state_seed, dtype, m, m_min, float(tol))
+        rid = ct.c_uint64()
+        _check(_lib.syk_engine_submit(self._h, ct.byref(r), ct.byref(rid)))
+        self._nt[rid.value] = t.size
+        return rid.value
+
+    def poll(self, wait_ms: int = -1):
+        """One finished request as a dict (F_raw, F_norm, F_imag, id, status, m_used,
+        footprint_bytes, t_submit, t_start, t_end, stats), or None if none finished."""
+        cap = max(self._nt.values(), default=1)
+        raw, nrm, im = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+        info = ResultInfo()
+        dp = lambda a: a.ctypes.data_as(_dp)
+        st = _lib.syk_engine_poll(self._h, wait_ms, ct.byref(info), dp(raw), dp(nrm), dp(im), cap)
+        if st == EAGAIN:
+            return None
+        _check(st)
+        self._nt.pop(info.id, None)
+        out = {f: getattr(info, f) for f, _ in ResultInfo._fields_ if f != "stats"}
+        out["stats"] = {f: getattr(info.stats, f) for f, _ in OtocStats._fields_}
+        out["F_raw"], out["F_norm"], out["F_imag"] = raw[:info.nt], nrm[:info.nt], im[:info.nt]
+        return out
+
+    def cancel(self, rid: int):
+        _check(_lib.syk_engine_cancel(self._h, rid))
+
+    def stats(self) -> dict:
+        s = EngineStats()
+        _check(_lib.syk_engine_get_stats(self._h, ct.byref(s)))
+        return {f: getattr(s, f) for f, _ in EngineStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_lib.syk_engine_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

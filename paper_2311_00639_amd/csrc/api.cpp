@@ -6,11 +6,16 @@
 #include <string>
 
 #include "apply_plan.hpp"
+#include "engine.hpp"
 #include "krylov.hpp"
 #include "otoc.hpp"
 
 struct syk_ham {
     syk::Hamiltonian h;
+};
+
+struct syk_engine {
+    std::unique_ptr<syk::Engine> e;
 };
 
 namespace {
@@ -52,13 +57,6 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 uint64_t block_amps(int N) { return 1ULL << (N / 2 - 1); }
 
 void check_N(int N) { require(N % 2 == 0 && N >= 6 && N <= 64, "N must be even with 6 <= N <= 64"); }
-
-void check_opts(const syk_krylov_opts &o) {
-    require(o.m >= 2 && o.m <= 128, "Krylov m must lie in [2, 128]");
-    require(o.tol > 0.0 && std::isfinite(o.tol), "Krylov tol must be positive");
-    require(o.reorth >= 0 && o.reorth <= 2, "reorth must be 0, 1 or 2");
-    require(o.max_substeps >= 0, "max_substeps must be >= 0");
-}
 
 }  // namespace
 
@@ -211,7 +209,7 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
         require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
         require(n_amps == block_amps(h->h.N), "n_amps must equal 2^(N/2-1)");
         require(std::isfinite(z_re) && std::isfinite(z_im), "z must be finite");
-        check_opts(*o);
+        syk::check_krylov_opts(*o);
         check_device();
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
         syk_krylov_stats st{};
@@ -236,48 +234,75 @@ syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t
                     double *F_raw, double *F_norm, double *F_imag, syk_otoc_stats *stats, void *stream) {
     return guarded([&] {
         require(h && t && o, "NULL argument");
-        const int N = h->h.N;
-        require(i >= 0 && i < N && j >= 0 && j < N && i != j, "Majorana indices must be distinct and in [0, N)");
-        require(nt >= 1, "nt must be >= 1");
-        require(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
-        require(o->nvec >= 1, "nvec must be >= 1");
-        require(o->autotune == 0 || o->autotune == 1, "autotune must be 0 or 1");
-        require(o->dtype == SYK_C64 || o->dtype == SYK_C128, "invalid dtype");
-        require(o->layout >= -1 && o->layout < std::max(N / 2 - 1, 1), "layout must be -1 or a rotation in [0, L)");
-        check_opts(o->krylov);
-        for (int k = 0; k < nt; ++k) {
-            require(std::isfinite(t[k]) && t[k] >= 0.0, "t must be finite and >= 0");
-            if (k) require(t[k] >= t[k - 1], "t must be non-decreasing");
-        }
+        syk::check_otoc_args(h->h.N, i, j, beta, t, nt, *o);
         check_device();
         auto t0 = std::chrono::steady_clock::now();
-        std::vector<double> ts(t, t + nt);
-        const bool prepend = ts[0] != 0.0;
-        if (prepend) ts.insert(ts.begin(), 0.0);
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
-        const uint64_t n = 1ULL << H.L;
         syk_otoc_stats st{};
-        std::vector<std::complex<double>> F;
-        auto &ws = syk::thread_workspace(0);
-        hipStream_t s = as_stream(stream);
-        if (o->dtype == SYK_C64) {
-            ws.ensure(syk::otoc_workspace_bytes(n, o->krylov.m, sizeof(float)));
-            syk::otoc_run<float>(H, i, j, beta, ts, *o, F, st, ws.ptr(), s);
-        } else {
-            ws.ensure(syk::otoc_workspace_bytes(n, o->krylov.m, sizeof(double)));
-            syk::otoc_run<double>(H, i, j, beta, ts, *o, F, st, ws.ptr(), s);
-        }
-        const double f0 = F[0].real();
-        const int off = prepend ? 1 : 0;
-        for (int k = 0; k < nt; ++k) {
-            const std::complex<double> f = F[k + off];
-            if (F_raw) F_raw[k] = f.real();
-            if (F_imag) F_imag[k] = f.imag();
-            if (F_norm) F_norm[k] = f.real() / f0;
-        }
+        syk::otoc_compute(H, i, j, beta, t, nt, *o, syk::thread_workspace(0), as_stream(stream), F_raw, F_norm,
+                          F_imag, st);
         st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (stats) *stats = st;
     });
+}
+
+syk_status syk_engine_create(const syk_engine_opts *o, syk_engine **out) {
+    return guarded([&] {
+        require(out != nullptr, "out is NULL");
+        *out = nullptr;
+        check_device();
+        syk_engine_opts d{};
+        if (o) {
+            require(o->max_active >= 0 && o->max_active <= 64, "max_active must lie in [0, 64]");
+            d = *o;
+        } else {
+            d.max_bypass = -1;
+        }
+        auto *e = new syk_engine();
+        try {
+            e->e.reset(new syk::Engine(d));
+        } catch (...) {
+            delete e;
+            throw;
+        }
+        *out = e;
+    });
+}
+
+syk_status syk_engine_submit(syk_engine *e, const syk_request *r, uint64_t *id) {
+    return guarded([&] {
+        require(e && r && id, "NULL argument");
+        *id = e->e->submit(*r);
+    });
+}
+
+syk_status syk_engine_poll(syk_engine *e, int wait_ms, syk_result_info *info, double *F_raw, double *F_norm,
+                           double *F_imag, int cap) {
+    syk_status st = SYK_OK;
+    const syk_status g = guarded([&] {
+        require(e && info, "NULL argument");
+        st = e->e->poll(wait_ms, *info, F_raw, F_norm, F_imag, cap);
+        if (st == SYK_EINVAL) syk::fail(SYK_EINVAL, "cap is smaller than the request's nt");
+    });
+    return g != SYK_OK ? g : st;
+}
+
+syk_status syk_engine_cancel(syk_engine *e, uint64_t id) {
+    return guarded([&] {
+        require(e != nullptr, "NULL argument");
+        e->e->cancel(id);
+    });
+}
+
+syk_status syk_engine_get_stats(syk_engine *e, syk_engine_stats *st) {
+    return guarded([&] {
+        require(e && st, "NULL argument");
+        e->e->stats(*st);
+    });
+}
+
+syk_status syk_engine_destroy(syk_engine *e) {
+    return guarded([&] { delete e; });
 }
 
 syk_status syk_workspace_bytes(int N, int m, syk_dtype dt, int nvec, uint64_t *bytes) {
@@ -385,6 +410,7 @@ const char *syk_status_string(syk_status s) {
         case SYK_ENOTCONV: return "SYK_ENOTCONV";
         case SYK_ENUMERIC: return "SYK_ENUMERIC";
         case SYK_ECANCELLED: return "SYK_ECANCELLED";
+        case SYK_EAGAIN: return "SYK_EAGAIN";
     }
     return "SYK_UNKNOWN";
 }

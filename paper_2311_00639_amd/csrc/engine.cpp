@@ -1,0 +1,345 @@
+// Request engine: continuous batching of OTOC requests on one device.
+//
+// Slots are host worker threads, each with its own HIP stream.  A free slot takes the
+// first queued request (in arrival order) whose device footprint fits in what the budget
+// has left; the oldest request may be overtaken by smaller ones only max_bypass times.
+// Requests admitted while others run share the GPU: their kernels are enqueued on
+// different streams and overlap.  Every request builds its own Hamiltonian (tables and
+// plans on this device), allocates its own workspace and runs the same code path as a
+// single syk_otoc call with autotune off, so its result does not depend on the mix.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "engine.hpp"
+#include "krylov.hpp"
+#include "otoc.hpp"
+
+namespace syk {
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t footprint_bytes(int N, double k, int m, syk_dtype dt) {
+    const uint64_t n = 1ULL << (N / 2 - 1);
+    const size_t e = (dt == SYK_C64) ? sizeof(float) : sizeof(double);
+    const uint64_t K = static_cast<uint64_t>(std::floor(k * N + 0.5));
+    // workspace + per-block term tables and tiled plans (tile map, records, groups)
+    return otoc_workspace_bytes(n, m, e) + 2 * ((n >> 8) + K * 256 + (1u << 16)) + (1u << 20);
+}
+
+struct Req {
+    uint64_t id = 0;
+    syk_request r{};
+    std::vector<double> t;
+    int m_used = 0;
+    uint64_t footprint = 0;
+    double t_submit = 0, t_start = 0;
+    int bypassed = 0;
+    std::atomic<int> cancel{0};
+};
+
+struct Done {
+    syk_result_info info{};
+    std::vector<double> raw, norm, imag;
+};
+
+}  // namespace
+
+struct Engine::Impl {
+    int dev = 0;
+    uint64_t budget = 0, in_use = 0, peak = 0;
+    int max_active = 4, max_bypass = 8;
+    Clock::time_point t0 = Clock::now();
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Req>> pending;
+    std::map<uint64_t, std::shared_ptr<Req>> running;
+    std::deque<Done> done;
+    std::vector<double> latencies;
+    long long submitted = 0, completed = 0, failed = 0, cancelled = 0;
+    double busy = 0, busy_since = 0;
+    uint64_t next_id = 1;
+    bool stop = false;
+    std::vector<std::thread> workers;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+    // caller holds mu
+    std::shared_ptr<Req> pick() {
+        if (pending.empty()) return nullptr;
+        const uint64_t avail = budget - in_use;
+        auto &head = pending.front();
+        if (head->footprint <= avail) {
+            auto r = head;
+            pending.pop_front();
+            return r;
+        }
+        if (head->bypassed >= max_bypass) return nullptr;
+        for (auto it = pending.begin() + 1; it != pending.end(); ++it) {
+            if ((*it)->footprint <= avail) {
+                auto r = *it;
+                pending.erase(it);
+                ++head->bypassed;
+                return r;
+            }
+        }
+        return nullptr;
+    }
+
+    void set_active_changed(int before, int after) {
+        const double t = now();
+        if (before == 0 && after > 0) busy_since = t;
+        if (before > 0 && after == 0) busy += t - busy_since;
+    }
+
+    Done run(Req &q, hipStream_t s) {
+        Done d;
+        d.info.id = q.id;
+        d.info.nt = q.r.nt;
+        d.info.m_used = q.m_used;
+        d.info.footprint_bytes = q.footprint;
+        d.info.t_submit = q.t_submit;
+        d.info.t_start = q.t_start;
+        d.raw.assign(q.r.nt, 0.0);
+        d.norm.assign(q.r.nt, 0.0);
+        d.imag.assign(q.r.nt, 0.0);
+        try {
+            Hamiltonian h;
+            build_hamiltonian(h, q.r.N, q.r.k, q.r.seed);
+            syk_otoc_opts o{};
+            o.nvec = q.r.nvec;
+            o.state_seed = q.r.state_seed;
+            o.dtype = q.r.dtype;
+            syk_krylov_default_opts(q.r.dtype, &o.krylov);
+            o.krylov.m = q.m_used;
+            if (q.r.tol > 0.0) o.krylov.tol = q.r.tol;
+            o.layout = -1;
+            o.autotune = 0;
+            DeviceBuffer ws;
+            syk_otoc_stats st{};
+            const auto c0 = Clock::now();
+            otoc_compute(h, q.r.i, q.r.j, q.r.beta, q.t.data(), q.r.nt, o, ws, s, d.raw.data(), d.norm.data(),
+                         d.imag.data(), st, &q.cancel);
+            SYK_HIP(hipStreamSynchronize(s));
+            st.seconds = std::chrono::duration<double>(Clock::now() - c0).count();
+            d.info.stats = st;
+            d.info.status = SYK_OK;
+        } catch (const Error &e) {
+            d.info.status = e.status;
+            hipStreamSynchronize(s);
+        } catch (const std::bad_alloc &) {
+            d.info.status = SYK_ENOMEM;
+        } catch (...) {
+            d.info.status = SYK_EDEVICE;
+            hipStreamSynchronize(s);
+        }
+        if (d.info.status != SYK_OK) {
+            d.raw.assign(q.r.nt, 0.0);
+            d.norm.assign(q.r.nt, 0.0);
+            d.imag.assign(q.r.nt, 0.0);
+        }
+        return d;
+    }
+
+    void worker() {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        hipStream_t s = nullptr;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
+        for (;;) {
+            std::shared_ptr<Req> q;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stop || (q = pick()) != nullptr; });
+                if (!q) break;                       // stop requested, nothing admitted
+                in_use += q->footprint;
+                peak = std::max(peak, in_use);
+                const int before = static_cast<int>(running.size());
+                running[q->id] = q;
+                set_active_changed(before, before + 1);
+                q->t_start = now();
+            }
+            Done d = run(*q, s);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                in_use -= q->footprint;
+                const int before = static_cast<int>(running.size());
+                running.erase(q->id);
+                set_active_changed(before, before - 1);
+                d.info.t_end = now();
+                if (d.info.status == SYK_OK) {
+                    ++completed;
+                    latencies.push_back(d.info.t_end - d.info.t_submit);
+                } else if (d.info.status == SYK_ECANCELLED) {
+                    ++cancelled;
+                } else {
+                    ++failed;
+                }
+                done.push_back(std::move(d));
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();                    // memory returned: others may fit now
+        }
+        hipStreamDestroy(s);
+    }
+};
+
+Engine::Engine(const syk_engine_opts &o) : p_(new Impl) {
+    SYK_HIP(hipGetDevice(&p_->dev));
+    uint64_t budget = o.budget_bytes;
+    if (budget == 0) {
+        size_t free_b = 0, total_b = 0;
+        SYK_HIP(hipMemGetInfo(&free_b, &total_b));
+        budget = static_cast<uint64_t>(0.85 * static_cast<double>(free_b));
+    }
+    p_->budget = budget;
+    p_->max_active = o.max_active > 0 ? o.max_active : 4;
+    p_->max_bypass = o.max_bypass >= 0 ? o.max_bypass : 8;
+    for (int w = 0; w < p_->max_active; ++w) p_->workers.emplace_back([this] { p_->worker(); });
+}
+
+Engine::~Engine() {
+    {
+        std::lock_guard<std::mutex> lk(p_->mu);
+        p_->stop = true;
+        p_->pending.clear();
+        for (auto &kv : p_->running) kv.second->cancel.store(1);
+    }
+    p_->cv_work.notify_all();
+    for (auto &t : p_->workers) t.join();
+}
+
+uint64_t Engine::submit(const syk_request &r) {
+    auto require = [](bool c, const char *msg) {
+        if (!c) fail(SYK_EINVAL, msg);
+    };
+    require(r.N % 2 == 0 && r.N >= 6 && r.N <= 64, "N must be even with 6 <= N <= 64");
+    require(std::isfinite(r.k) && r.k > 0.0, "k must be positive");
+    const double K = std::floor(r.k * r.N + 0.5);
+    const double nsub = static_cast<double>(r.N) * (r.N - 1) * (r.N - 2) * (r.N - 3) / 24.0;
+    require(K >= 1.0 && K <= nsub, "K = round(k N) must lie in [1, C(N,4)]");
+    syk_otoc_opts o{};
+    o.nvec = r.nvec;
+    o.state_seed = r.state_seed;
+    o.dtype = r.dtype;
+    require(r.dtype == SYK_C64 || r.dtype == SYK_C128, "invalid dtype");
+    syk_krylov_default_opts(r.dtype, &o.krylov);
+    const int m = r.m > 0 ? r.m : 30;
+    const int m_min = r.m_min > 0 ? r.m_min : std::min(m, 8);
+    require(m_min <= m, "m_min must not exceed m");
+    o.krylov.m = m;
+    if (r.tol > 0.0) o.krylov.tol = r.tol;
+    o.layout = -1;
+    check_otoc_args(r.N, r.i, r.j, r.beta, r.t, r.nt, o);
+    o.krylov.m = m_min;
+    check_krylov_opts(o.krylov);
+
+    auto q = std::make_shared<Req>();
+    q->r = r;
+    q->t.assign(r.t, r.t + r.nt);
+    q->r.t = nullptr;
+    q->m_used = m;
+    std::lock_guard<std::mutex> lk(p_->mu);
+    if (p_->stop) fail(SYK_EINVAL, "engine is shutting down");
+    while (q->m_used > m_min && footprint_bytes(r.N, r.k, q->m_used, r.dtype) > p_->budget) --q->m_used;
+    q->footprint = footprint_bytes(r.N, r.k, q->m_used, r.dtype);
+    if (q->footprint > p_->budget) fail(SYK_ENOMEM, "request footprint at m_min exceeds the engine budget");
+    q->id = p_->next_id++;
+    q->t_submit = p_->now();
+    p_->pending.push_back(q);
+    ++p_->submitted;
+    p_->cv_work.notify_all();
+    return q->id;
+}
+
+syk_status Engine::poll(int wait_ms, syk_result_info &info, double *raw, double *norm, double *imag, int cap) {
+    std::unique_lock<std::mutex> lk(p_->mu);
+    auto ready = [&] { return !p_->done.empty(); };
+    if (wait_ms < 0) {
+        p_->cv_done.wait(lk, [&] { return ready() || (p_->pending.empty() && p_->running.empty()); });
+    } else if (wait_ms > 0) {
+        p_->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), ready);
+    }
+    if (!ready()) return SYK_EAGAIN;
+    Done &d = p_->done.front();
+    if (cap < d.info.nt) return SYK_EINVAL;
+    info = d.info;
+    for (int k = 0; k < d.info.nt; ++k) {
+        if (raw) raw[k] = d.raw[k];
+        if (norm) norm[k] = d.norm[k];
+        if (imag) imag[k] = d.imag[k];
+    }
+    p_->done.pop_front();
+    return SYK_OK;
+}
+
+void Engine::cancel(uint64_t id) {
+    {
+        std::lock_guard<std::mutex> lk(p_->mu);
+        auto rit = p_->running.find(id);
+        if (rit != p_->running.end()) {
+            rit->second->cancel.store(1);
+            return;
+        }
+        for (auto it = p_->pending.begin(); it != p_->pending.end(); ++it) {
+            if ((*it)->id != id) continue;
+            Done d;
+            d.info.id = id;
+            d.info.status = SYK_ECANCELLED;
+            d.info.nt = (*it)->r.nt;
+            d.info.m_used = (*it)->m_used;
+            d.info.footprint_bytes = (*it)->footprint;
+            d.info.t_submit = (*it)->t_submit;
+            d.info.t_start = d.info.t_end = p_->now();
+            d.raw.assign(d.info.nt, 0.0);
+            d.norm.assign(d.info.nt, 0.0);
+            d.imag.assign(d.info.nt, 0.0);
+            p_->pending.erase(it);
+            ++p_->cancelled;
+            p_->done.push_back(std::move(d));
+            p_->cv_done.notify_all();
+            p_->cv_work.notify_all();
+            return;
+        }
+    }
+    fail(SYK_EINVAL, "unknown or finished request id");
+}
+
+void Engine::stats(syk_engine_stats &st) {
+    std::lock_guard<std::mutex> lk(p_->mu);
+    st = syk_engine_stats{};
+    st.submitted = p_->submitted;
+    st.completed = p_->completed;
+    st.failed = p_->failed;
+    st.cancelled = p_->cancelled;
+    st.queued = static_cast<int>(p_->pending.size());
+    st.active = static_cast<int>(p_->running.size());
+    st.budget_bytes = p_->budget;
+    st.bytes_in_use = p_->in_use;
+    st.peak_bytes = p_->peak;
+    st.busy_seconds = p_->busy + (p_->running.empty() ? 0.0 : p_->now() - p_->busy_since);
+    std::vector<double> l = p_->latencies;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        // nearest-rank percentiles
+        auto pct = [&](double q) {
+            size_t r = static_cast<size_t>(std::ceil(q * static_cast<double>(l.size())));
+            r = std::min(std::max<size_t>(r, 1), l.size());
+            return l[r - 1];
+        };
+        st.p50_latency_s = pct(0.50);
+        st.p99_latency_s = pct(0.99);
+    }
+}
+
+}  // namespace syk

@@ -140,6 +140,16 @@ void ApplyTimer::flush() {
 // ------------------------------------------------------------------ Lanczos driver
 static int log2_of(uint64_t n) { return 63 - __builtin_clzll(n); }
 
+void check_krylov_opts(const syk_krylov_opts &o) {
+    auto require = [](bool c, const char *msg) {
+        if (!c) fail(SYK_EINVAL, msg);
+    };
+    require(o.m >= 2 && o.m <= 128, "Krylov m must lie in [2, 128]");
+    require(o.tol > 0.0 && std::isfinite(o.tol), "Krylov tol must be positive");
+    require(o.reorth >= 0 && o.reorth <= 2, "reorth must be 0, 1 or 2");
+    require(o.max_substeps >= 0, "max_substeps must be >= 0");
+}
+
 size_t krylov_workspace_bytes(uint64_t n, int m, size_t elem_bytes) {
     const size_t vec = static_cast<size_t>(n) * 2 * elem_bytes;
     const size_t part = static_cast<size_t>(reduction_blocks(n)) * 2 * (m + 2) * sizeof(double);

@@ -24,6 +24,9 @@ class TriExp {
     std::vector<double> lam_, Z_;
 };
 
+// Argument checks of Krylov options (throws SYK_EINVAL).
+void check_krylov_opts(const syk_krylov_opts &o);
+
 size_t krylov_workspace_bytes(uint64_t n, int m, size_t elem_bytes);
 
 // Optional timing of apply_H launches with HIP events recorded on the launch stream.

@@ -46,7 +46,8 @@ void apply_gamma(int N, int n, int src, int rot, const T *x, T *y, uint64_t amps
 
 template <typename T>
 void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<double> &ts, const syk_otoc_opts &o,
-              std::vector<std::complex<double>> &F, syk_otoc_stats &st, char *ws, hipStream_t s) {
+              std::vector<std::complex<double>> &F, syk_otoc_stats &st, char *ws, hipStream_t s,
+              const std::atomic<int> *cancel) {
     const uint64_t n = 1ULL << h.L;
     const size_t vb = up(static_cast<size_t>(n) * 2 * sizeof(T));
     T *l = reinterpret_cast<T *>(ws);
@@ -112,6 +113,7 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
                 F[k] += 0.25 * cd(hd[0], hd[1]);
                 ++done;
                 if (o.progress) o.progress(o.progress_ctx, done, total);
+                if (cancel && cancel->load()) fail(SYK_ECANCELLED, "request cancelled");
             }
         }
     }
@@ -123,9 +125,55 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
 }
 
 template void otoc_run<float>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
-                              std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t);
+                              std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t,
+                              const std::atomic<int> *);
 template void otoc_run<double>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
-                               std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t);
+                               std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t,
+                               const std::atomic<int> *);
+
+void check_otoc_args(int N, int i, int j, double beta, const double *t, int nt, const syk_otoc_opts &o) {
+    auto require = [](bool c, const char *msg) {
+        if (!c) fail(SYK_EINVAL, msg);
+    };
+    require(t != nullptr, "NULL argument");
+    require(i >= 0 && i < N && j >= 0 && j < N && i != j, "Majorana indices must be distinct and in [0, N)");
+    require(nt >= 1, "nt must be >= 1");
+    require(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
+    require(o.nvec >= 1, "nvec must be >= 1");
+    require(o.autotune == 0 || o.autotune == 1, "autotune must be 0 or 1");
+    require(o.dtype == SYK_C64 || o.dtype == SYK_C128, "invalid dtype");
+    require(o.layout >= -1 && o.layout < std::max(N / 2 - 1, 1), "layout must be -1 or a rotation in [0, L)");
+    check_krylov_opts(o.krylov);
+    for (int k = 0; k < nt; ++k) {
+        require(std::isfinite(t[k]) && t[k] >= 0.0, "t must be finite and >= 0");
+        if (k) require(t[k] >= t[k - 1], "t must be non-decreasing");
+    }
+}
+
+void otoc_compute(Hamiltonian &H, int i, int j, double beta, const double *t, int nt, const syk_otoc_opts &o,
+                  DeviceBuffer &ws, hipStream_t s, double *F_raw, double *F_norm, double *F_imag,
+                  syk_otoc_stats &st, const std::atomic<int> *cancel) {
+    std::vector<double> ts(t, t + nt);
+    const bool prepend = ts[0] != 0.0;
+    if (prepend) ts.insert(ts.begin(), 0.0);
+    const uint64_t n = 1ULL << H.L;
+    std::vector<std::complex<double>> F;
+    if (o.dtype == SYK_C64) {
+        ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(float)));
+        otoc_run<float>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel);
+    } else {
+        ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(double)));
+        otoc_run<double>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel);
+    }
+    const double f0 = F[0].real();
+    const int off = prepend ? 1 : 0;
+    for (int k = 0; k < nt; ++k) {
+        const std::complex<double> f = F[k + off];
+        if (F_raw) F_raw[k] = f.real();
+        if (F_imag) F_imag[k] = f.imag();
+        if (F_norm) F_norm[k] = f.real() / f0;
+    }
+}
 template void apply_gamma<float>(int, int, int, int, const float *, float *, uint64_t, hipStream_t);
 template void apply_gamma<double>(int, int, int, int, const double *, double *, uint64_t, hipStream_t);
 

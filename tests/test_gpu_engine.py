@@ -1,0 +1,172 @@
+"""Request engine (continuous batching) on the GPU, through the C ABI.
+
+* Each result is the same alone (syk_otoc on its own, autotune off) and in a mix of
+  concurrently admitted requests of different N, k and beta: within the stated
+  mixed-precision tolerance 1e-5 on F (complex64 states), and the oracle agrees at N = 16
+  (complex128, 1e-9).
+* Admission respects the memory budget (peak bytes in use never exceed it; requests that
+  do not fit wait, smaller ones overtake within the bypass limit).
+* Under memory pressure the Krylov dimension is lowered, never below m_min, and the result
+  still meets the tolerance.
+* Cancellation of queued and running requests; oversized and invalid requests are refused.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2311_00639_amd as syk  # noqa: E402
+from oracle import dense, ensemble, haar  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TS = [0.0, 0.5, 1.0, 1.5, 2.0, 3.0]
+WAIT_MS = 120000
+
+
+def drain(eng, n):
+    out = {}
+    for _ in range(n):
+        r = eng.poll(WAIT_MS)
+        assert r is not None, "engine produced no result within the wait"
+        out[r["id"]] = r
+    return out
+
+
+def alone(N, k, seed, beta, dtype, m, state_seed=7, nvec=1):
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    raw, nrm, im, _ = syk.otoc(h, N - 1, N - 2, beta, TS, nvec=nvec, state_seed=state_seed, dtype=dtype, m=m,
+                               autotune=False)
+    h.close()
+    return raw, nrm, im
+
+
+MIX = [  # N, k, seed, beta
+    (24, 2, 11, 2.0),
+    (32, 4, 12, 5.0),
+    (40, 1, 13, 1.0),
+    (28, 8, 14, 10.0),
+    (36, 2, 15, 0.5),
+    (24, 4, 16, 20.0),
+]
+
+
+def test_engine_results_equal_alone_and_in_mix():
+    torch.cuda.set_device(0)
+    eng = syk.Engine(max_active=4)
+    ids = {}
+    for (N, k, seed, beta) in MIX:
+        ids[eng.submit(N, k, seed, beta, TS, state_seed=7, dtype=syk.C64, m=30)] = (N, k, seed, beta)
+    got = drain(eng, len(MIX))
+    st = eng.stats()
+    eng.close()
+    assert st["completed"] == len(MIX) and st["failed"] == 0
+    assert st["p50_latency_s"] > 0 and st["p99_latency_s"] >= st["p50_latency_s"]
+    overlapped = False
+    res = sorted(got.values(), key=lambda r: r["t_start"])
+    for a, b in zip(res, res[1:]):
+        overlapped |= b["t_start"] < a["t_end"]
+    assert overlapped, "no two requests ran at the same time"
+    for rid, (N, k, seed, beta) in ids.items():
+        r = got[rid]
+        assert r["status"] == 0 and r["m_used"] == 30
+        raw, nrm, im = alone(N, k, seed, beta, syk.C64, 30)
+        d = max(np.abs(r["F_raw"] - raw).max(), np.abs(r["F_imag"] - im).max())
+        print(f"N={N} k={k} beta={beta}: |engine - alone| = {d:.3e}")
+        assert d <= 1e-5
+        assert np.abs(r["F_norm"] - nrm).max() <= 1e-5 / abs(raw[0]) * 2
+
+
+def test_engine_matches_oracle_small_N():
+    torch.cuda.set_device(0)
+    N, k, seed, beta, ss = 16, 4, 3, 2.0, 21
+    eng = syk.Engine(max_active=2)
+    rid = eng.submit(N, k, seed, beta, TS, state_seed=ss, dtype=syk.C128, m=30)
+    other = eng.submit(20, 2, 4, 1.0, TS, state_seed=1, dtype=syk.C64, m=20)   # runs beside it
+    got = drain(eng, 2)
+    eng.close()
+    assert got[other]["status"] == 0
+    r = got[rid]
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    H = dense.hamiltonian(N, subs, J)
+    ch = dense.chis(N)
+    F = dense.otoc_state(H, ch[N - 1], ch[N - 2], beta, TS, haar.haar_state(N, ss, 0))
+    ref_raw, ref_nrm, ref_im = dense.normalise_curves(F[None, :])
+    assert np.abs(r["F_raw"] - ref_raw).max() <= 1e-9
+    assert np.abs(r["F_imag"] - ref_im).max() <= 1e-9
+    assert np.abs(r["F_norm"] - ref_nrm).max() <= 1e-8
+
+
+def test_engine_admission_respects_budget():
+    torch.cuda.set_device(0)
+    big = syk.workspace_bytes(40, 30, syk.C64)
+    small = syk.workspace_bytes(24, 30, syk.C64)
+    budget = int(big * 1.3)                       # one N = 40 request at a time
+    eng = syk.Engine(budget_bytes=budget, max_active=4, max_bypass=8)
+    b1 = eng.submit(40, 2, 1, 1.0, TS, dtype=syk.C64)
+    b2 = eng.submit(40, 2, 2, 1.0, TS, dtype=syk.C64)
+    s1 = eng.submit(24, 2, 3, 1.0, TS, dtype=syk.C64)
+    got = drain(eng, 3)
+    st = eng.stats()
+    eng.close()
+    assert all(r["status"] == 0 for r in got.values())
+    assert st["peak_bytes"] <= budget
+    assert got[b1]["footprint_bytes"] >= big and got[s1]["footprint_bytes"] >= small
+    # the two large requests never overlap; the small one overtakes the waiting large one
+    a, b = sorted([got[b1], got[b2]], key=lambda r: r["t_start"])
+    assert b["t_start"] >= a["t_end"]
+    assert got[s1]["t_start"] < got[b2]["t_start"]
+
+
+def test_engine_lowers_krylov_dimension_under_memory_pressure():
+    torch.cuda.set_device(0)
+    N, k, seed, beta = 32, 4, 5, 5.0
+    budget = syk.workspace_bytes(N, 12, syk.C64) + (4 << 20)
+    eng = syk.Engine(budget_bytes=budget, max_active=1)
+    rid = eng.submit(N, k, seed, beta, TS, state_seed=7, dtype=syk.C64, m=30, m_min=6)
+    r = drain(eng, 1)[rid]
+    eng.close()
+    assert r["status"] == 0 and 6 <= r["m_used"] < 30
+    raw, _, im = alone(N, k, seed, beta, syk.C64, 30)
+    assert np.abs(r["F_raw"] - raw).max() <= 1e-5
+    assert np.abs(r["F_imag"] - im).max() <= 1e-5
+
+
+def test_engine_cancel_queued_and_running():
+    torch.cuda.set_device(0)
+    eng = syk.Engine(max_active=1)
+    long_t = np.arange(0.0, 40.0, 0.25)
+    run_id = eng.submit(40, 4, 1, 10.0, long_t, dtype=syk.C64)
+    queued = eng.submit(24, 2, 2, 1.0, TS, dtype=syk.C64)
+    eng.cancel(queued)
+    t0 = time.time()
+    while eng.stats()["active"] == 0 and time.time() - t0 < 60:
+        time.sleep(0.01)
+    assert eng.stats()["active"] == 1
+    eng.cancel(run_id)
+    got = drain(eng, 2)
+    with pytest.raises(syk.SykError):
+        eng.cancel(queued)                        # already finished
+    eng.close()
+    assert got[queued]["status"] == syk.ECANCELLED
+    assert got[run_id]["status"] == syk.ECANCELLED
+
+
+def test_engine_refuses_bad_requests():
+    torch.cuda.set_device(0)
+    eng = syk.Engine(budget_bytes=1 << 20, max_active=1)
+    with pytest.raises(syk.SykError) as e:
+        eng.submit(40, 2, 1, 1.0, TS)             # cannot fit even at m_min
+    assert e.value.status == 3
+    for bad in [dict(N=41), dict(k=-1.0), dict(beta=-1.0), dict(t=[1.0, 0.5]), dict(i=3, j=3)]:
+        args = dict(N=16, k=2.0, seed=1, beta=1.0, t=TS)
+        args.update(bad)
+        with pytest.raises(syk.SykError) as e:
+            eng.submit(**args)
+        assert e.value.status == 1
+    assert eng.poll(0) is None
+    st = eng.stats()
+    eng.close()
+    assert st["submitted"] == 0

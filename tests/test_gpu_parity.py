@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the oracle on the same seeded inputs.
 
-Tolerances (derivations in DESIGN.md, "Tolerances"):
+Tolerances:
 * complex128 apply_H: ||y - y_ref|| / ||y_ref|| <= 1e-10 (stated target; observed ~1e-16).
 * complex64 apply_H: the input is rounded to complex64 first and the oracle evaluates the
   rounded input in float64, so only the float32 accumulation of <= K terms differs:
