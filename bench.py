@@ -16,6 +16,15 @@ HIP-event timings of every apply_H launch in the timed region, and cpu_baseline 
 oracle's matrix-free row evaluation timed on a bounded sample, scaled by the
 term-amplitudes one realisation needs.
 
+Also reported, outside the timed region:
+* mixed_precision: the same realisation, Haar state and beta = 10 evaluated with
+  complex128 states at t = 0, 5, 10, 20, and the complex64 curve's deviation from it
+  there (the error of the mixed-precision path, per result);
+* serving: the request engine under a Poisson stream of OTOC requests (N uniform in
+  {32, 36, 40, 44, 48}, k uniform in {1, 2, 4, 8}, beta = 10, t = 0:0.5:5, complex64,
+  one Haar state, request seed 50000 + id) at a fixed offered rate for a fixed window,
+  with p50/p99 submit-to-finish latency and completed realisations per hour.
+
 --pmc-sample runs a short chain (one beta, t = 0, 0.25, 0.5) in the identical launch
 configuration plus a 1 GiB device copy, for hardware-counter passes.
 """
@@ -72,6 +81,70 @@ def cpu_baseline(term_amps_per_realisation: float, seconds_target: float = 12.0)
                       f"{term_amps_per_realisation:.3e} term-amps per realisation measured on the GPU"}
 
 
+def mixed_precision_check(syk, curve_c64, stream):
+    """complex128 reference of the timed beta = 10 curve at a few t points."""
+    t_check = [0.0, 5.0, 10.0, 20.0]
+    h = syk.create_hamiltonian(N, 4, K_SPARSITY, SEED)
+    syk.autotune(h, syk.C128, stream=stream)
+    t0 = time.perf_counter()
+    raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, 10.0, t_check, nvec=1, state_seed=STATE_SEED, dtype=syk.C128,
+                                m=M_KRYLOV, stream=stream)
+    secs = time.perf_counter() - t0
+    h.close()
+    ts = t_grid()
+    idx = [ts.index(t) for t in t_check]
+    c_raw, c_nrm, c_im = (curve_c64[0][idx], curve_c64[1][idx], curve_c64[2][idx])
+    return {"t": t_check, "F_norm_c128": [float(v) for v in nrm], "F_norm_c64": [float(v) for v in c_nrm],
+            "abs_err_F_norm": [float(abs(a - b)) for a, b in zip(c_nrm, nrm)],
+            "abs_err_F_raw": [float(abs(a - b)) for a, b in zip(c_raw, raw)],
+            "abs_err_F_imag": [float(abs(a - b)) for a, b in zip(c_im, im)],
+            "max_abs_err": float(max(max(abs(a - b) for a, b in zip(c_nrm, nrm)),
+                                     max(abs(a - b) for a, b in zip(c_raw, raw)))),
+            "tolerance": 1e-5, "c128_seconds": secs, "c128_matvecs": st["matvecs"]}
+
+
+def serving_leg(syk, rate_hz=4.0, window_s=30.0, drain_s=60.0, seed=500):
+    """Poisson stream of OTOC requests into the engine (continuous batching)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    Ns, ks = (32, 36, 40, 44, 48), (1, 2, 4, 8)
+    ts = [0.5 * n for n in range(11)]
+    arrivals, t = [], 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_hz)
+        if t > window_s:
+            break
+        arrivals.append((t, int(rng.choice(Ns)), int(rng.choice(ks))))
+    eng = syk.Engine(max_active=4)
+    start = time.perf_counter()
+    done, i, failed = 0, 0, 0
+    while done < len(arrivals):
+        now = time.perf_counter() - start
+        while i < len(arrivals) and arrivals[i][0] <= now:
+            _, n_maj, k = arrivals[i]
+            eng.submit(n_maj, k, 50000 + i, 10.0, ts, state_seed=50000 + i, dtype=syk.C64, m=30)
+            i += 1
+        if now > window_s + drain_s:
+            break
+        nxt = arrivals[i][0] - now if i < len(arrivals) else 0.5
+        r = eng.poll(max(1, int(1000 * min(nxt, 0.5))))
+        if r is not None:
+            done += 1
+            failed += r["status"] != 0
+            if done % 25 == 0:
+                print(f"[bench] serving: {done}/{len(arrivals)} requests done, {now:.0f} s", file=sys.stderr,
+                      flush=True)
+    wall = time.perf_counter() - start
+    st = eng.stats()
+    eng.close()
+    return {"requests": len(arrivals), "completed": st["completed"], "failed": st["failed"] + failed,
+            "offered_rate_per_s": rate_hz, "window_s": window_s, "wall_s": wall,
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "realisations_per_h": 3600.0 * st["completed"] / wall,
+            "busy_s": st["busy_seconds"], "peak_bytes": st["peak_bytes"], "max_active": 4,
+            "mix": "N in {32,36,40,44,48}, k in {1,2,4,8}, beta=10, t=0:0.5:5, c64, m=30, 1 Haar state"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,6 +152,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -181,6 +256,11 @@ def main():
                      "kernel": "apply_h_tiled", "launches_timed": launches},
         "otoc_F_norm": {str(b): [float(r[1][i]) for i in (4, 20, 40, 80)] for b, r in results},
     }
+    c10 = [r for b, r in results if b == 10.0]
+    if not args.no_precision and c10:
+        rec["mixed_precision"] = mixed_precision_check(syk, c10[0], stream)
+    if not args.no_serving:
+        rec["serving"] = serving_leg(syk)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(term_amps_per_real)
     print(json.dumps(rec), flush=True)

@@ -198,6 +198,60 @@ syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t
                     const syk_otoc_opts *o, double *F_raw, double *F_norm, double *F_imag,
                     syk_otoc_stats *stats, void *stream);
 
+/* Green function of the supplement (Sec. I, random-state estimator) for chi_n,
+ *   G_v(t) = <psi| e^{(it-b/2)H} chi_n e^{-iHt} chi_n e^{-bH/2} |psi>,
+ * evaluated as the sum of its U-block and D-block chains (l = e^{-itH_A} e^{-bH_A/2} psi_A and
+ * r = e^{-itH_B} chi_n^{BA} e^{-bH_A/2} psi_A, both advanced incrementally in t; G_A = <l,
+ * chi_n^{AB} r>).  chi_n = gamma_n / sqrt 2, so G(0) = <psi|e^{-bH}|psi> / 2 (1/2 at b = 0);
+ * the paper's G_R(t) = Re G(t) / G(0) is G_norm.  n in [0, N); the paper uses n = N-1.
+ * Options, outputs (G_raw = mean_v Re G_v, G_imag = mean_v Im G_v, G_norm = G_raw /
+ * G_raw(t = 0)), synchronisation and errors as for syk_otoc. */
+syk_status syk_green(const syk_ham *h, int n, double beta, const double *t, int nt, const syk_otoc_opts *o,
+                     double *G_raw, double *G_norm, double *G_imag, syk_otoc_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------- batched OTOC */
+/* Many small-N realisations and random vectors in one persistent launch: the OTOC of
+ * syk_otoc for every item (W = chi_i, V = chi_j) at a common beta and t grid, nvec Haar
+ * vectors each (vector v of item r uses syk_haar_state(N, state_seed, v)), complex64
+ * states with double reductions and small exponential.  One workgroup runs one (item,
+ * vector) job at a time, entirely on the device (Haar state, Majorana insertions, Lanczos
+ * propagators with step control, overlaps), taking jobs from a device counter until none
+ * is left.  The launch shape (threads per workgroup, LDS chunk, workgroups per CU) is
+ * chosen by timing the eligible shapes on a sample of the batch unless `variant` >= 0.
+ * Block sizes: 8 <= N/2 - 1 <= 15 (N from 18 to 32) for the shapes that serve them. */
+typedef struct {
+    int N;                 /* Majoranas (even) */
+    double k;              /* sparsity, K = round(k N) */
+    uint64_t seed;         /* realisation (syk_create_hamiltonian) */
+    int i, j;              /* W = chi_i, V = chi_j, distinct, in [0, N) */
+    uint64_t state_seed;
+} syk_batch_item;
+
+typedef struct {
+    int nvec;              /* Haar vectors per item (>= 1) */
+    double beta;
+    int m;                 /* Krylov dimension, 2..60 */
+    double tol;            /* per-propagation tolerance (> 0) */
+    int variant;           /* launch shape, -1 = timed choice */
+    int max_substeps;      /* per job over all its propagations, 0 = 20000 */
+} syk_batch_opts;
+
+typedef struct {
+    long long matvecs;     /* over all jobs */
+    int n_jobs, slots, variant;
+    double kernel_ms;      /* the persistent launch, HIP events */
+    double tuned_ms[3];    /* sample timings of shapes 0..2 (-1: not timed) */
+    double seconds;        /* wall time of the call */
+} syk_batch_stats;
+
+/* F_raw, F_norm, F_imag: host, n_items x nt doubles (row r = item r; any may be NULL),
+ * as syk_otoc's outputs of each item.  t: host, nt non-decreasing times >= 0.  Synchronises
+ * `stream`.  Errors: EINVAL, EUNSUPPORTED (block size outside every shape), ENOMEM,
+ * EDEVICE, ENOTCONV, ENUMERIC. */
+syk_status syk_otoc_batch(const syk_batch_item *items, int n_items, const double *t, int nt,
+                          const syk_batch_opts *o, double *F_raw, double *F_norm, double *F_imag,
+                          syk_batch_stats *stats, void *stream);
+
 /* ---------------------------------------------------------------- request engine */
 /* Serving engine: OTOC requests of mixed N, k and seed (one disorder realisation each,
  * the quantity of syk_otoc) taken as they arrive, with continuous batching: a request is
@@ -294,17 +348,18 @@ syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, doub
                             double *c_re, double *c_im);
 
 /* Launch plan of the tiled apply_H kernel for one block (host-only; no GPU needed).
- * Blocks of 2^L amplitudes with L >= tile_bits + 5 are served by the tiled kernel: output
- * tiles of 2^tile_bits amplitudes, terms grouped by partner tile (n_groups groups), tiles
- * mapped to workgroups so that the ones resident on one XCD form a coset of a 5-dim
- * subspace (classes5 = partner-tile classes modulo it) and those on the GPU one of an
- * 8-dim subspace (classes8).  rot is the vector layout: index bit b holds qubit
- * (b + rot) mod L.  layout = -1 asks for the planner's choice (the layout syk_otoc uses by
- * default), layout >= 0 for that rotation. */
+ * Blocks of 2^L amplitudes with L >= 18 are served by the tiled kernel: output tiles of
+ * 2^tile_bits amplitudes, terms grouped by partner tile (n_groups groups), tiles mapped
+ * to workgroups so that the 2^res_bits tiles resident on one XCD form a coset of a
+ * res_bits-dim subspace (classes_xcd = partner-tile classes modulo it, which sets the L2
+ * misses) and those on the whole GPU one of a (res_bits + 3)-dim subspace (classes_gpu).
+ * rot is the vector layout: index bit b holds qubit (b + rot) mod L.  layout = -1 asks
+ * for the planner's choice (the layout syk_otoc uses by default), layout >= 0 for that
+ * rotation. */
 typedef struct {
     int tiled;             /* 0: the block is served by the per-amplitude gather kernel */
     int variant;           /* compiled kernel variant in use (default or tuned) */
-    int tile_bits, rot, n_groups, classes5, classes8;
+    int tile_bits, rot, n_groups, classes_xcd, classes_gpu, res_bits;
     uint64_t n_tiles;
 } syk_plan_desc;
 syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, syk_plan_desc *out);
@@ -316,6 +371,12 @@ syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int 
  * apply with variant v (-1 where skipped).  Uses a library-owned workspace of two vectors.
  * Errors: EINVAL, ENOMEM, EDEVICE. */
 syk_status syk_autotune(const syk_ham *h, syk_dtype dt, int *variant, float *ms, int cap, void *stream);
+
+/* Pin the tiled apply_H variant (0 <= variant < the number of entries syk_autotune
+ * reports) for this handle, precision and the current device, in place of the default or
+ * tuned one: for tests of every variant and for reproducible timings.  Host-only apart
+ * from querying the current device.  Errors: EINVAL. */
+syk_status syk_select_variant(const syk_ham *h, syk_dtype dt, int variant);
 
 /* Release the library's cached device workspaces on the current device. */
 syk_status syk_release_workspace(void);

@@ -24,13 +24,16 @@ from ._lib import (  # noqa: F401
     apply_majorana,
     autotune,
     create_hamiltonian,
+    green,
     haar_state,
     kernel_revision,
     krylov_expm,
     library_path,
     otoc,
+    otoc_batch,
     plan_describe,
     release_workspace,
+    select_variant,
     tridiag_expm,
     workspace_bytes,
 )

@@ -55,7 +55,8 @@ class OtocOpts(ct.Structure):
 class PlanDesc(ct.Structure):
     _fields_ = [("tiled", ct.c_int), ("variant", ct.c_int), ("tile_bits", ct.c_int), ("rot", ct.c_int),
                 ("n_groups", ct.c_int),
-                ("classes5", ct.c_int), ("classes8", ct.c_int), ("n_tiles", ct.c_uint64)]
+                ("classes_xcd", ct.c_int), ("classes_gpu", ct.c_int), ("res_bits", ct.c_int),
+                ("n_tiles", ct.c_uint64)]
 
 
 class OtocStats(ct.Structure):
@@ -87,6 +88,21 @@ class EngineStats(ct.Structure):
                 ("p50_latency_s", ct.c_double), ("p99_latency_s", ct.c_double), ("busy_seconds", ct.c_double)]
 
 
+class BatchItem(ct.Structure):
+    _fields_ = [("N", ct.c_int), ("k", ct.c_double), ("seed", ct.c_uint64), ("i", ct.c_int), ("j", ct.c_int),
+                ("state_seed", ct.c_uint64)]
+
+
+class BatchOpts(ct.Structure):
+    _fields_ = [("nvec", ct.c_int), ("beta", ct.c_double), ("m", ct.c_int), ("tol", ct.c_double),
+                ("variant", ct.c_int), ("max_substeps", ct.c_int)]
+
+
+class BatchStats(ct.Structure):
+    _fields_ = [("matvecs", ct.c_longlong), ("n_jobs", ct.c_int), ("slots", ct.c_int), ("variant", ct.c_int),
+                ("kernel_ms", ct.c_double), ("tuned_ms", ct.c_double * 3), ("seconds", ct.c_double)]
+
+
 _vp, _u64, _i, _d = ct.c_void_p, ct.c_uint64, ct.c_int, ct.c_double
 _dp = ct.POINTER(ct.c_double)
 _SIGS = {
@@ -104,6 +120,10 @@ _SIGS = {
     "syk_release_workspace": [],
     "syk_plan_describe": [_vp, _i, _i, _i, ct.POINTER(PlanDesc)],
     "syk_autotune": [_vp, _i, ct.POINTER(_i), ct.POINTER(ct.c_float), _i, _vp],
+    "syk_select_variant": [_vp, _i, _i],
+    "syk_otoc_batch": [ct.POINTER(BatchItem), _i, _dp, _i, ct.POINTER(BatchOpts), _dp, _dp, _dp,
+                       ct.POINTER(BatchStats), _vp],
+    "syk_green": [_vp, _i, _d, _dp, _i, ct.POINTER(OtocOpts), _dp, _dp, _dp, ct.POINTER(OtocStats), _vp],
     "syk_engine_create": [ct.POINTER(EngineOpts), ct.POINTER(_vp)],
     "syk_engine_submit": [_vp, ct.POINTER(Request), ct.POINTER(_u64)],
     "syk_engine_poll": [_vp, _i, ct.POINTER(ResultInfo), _dp, _dp, _dp, _i],
@@ -142,6 +162,8 @@ def _ptr(a):
 def _stream(stream):
     if stream is None:
         import torch
+        if not torch.cuda.is_available():
+            return None          # the library reports the missing device itself
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, int):
         return stream
@@ -285,6 +307,53 @@ def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_
     return raw, nrm, im, {f: getattr(st, f) for f, _ in OtocStats._fields_}
 
 
+def green(ham: Hamiltonian, n: int, beta: float, t, nvec: int = 1, state_seed: int = 0, dtype: int = C128,
+          m: int = None, tol: float = None, profile: bool = False, layout: int = -1, autotune: bool = True,
+          stream=None):
+    """Green function of chi_n by the random-state estimator (syk_green).  Returns
+    (G_raw, G_norm, G_imag, stats); G_norm is the paper's G_R(t) = Re G(t) / G(0)."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    nt = t.size
+    o = OtocOpts()
+    o.nvec = nvec
+    o.state_seed = state_seed
+    o.dtype = dtype
+    o.krylov = default_krylov_opts(dtype)
+    o.profile = 1 if profile else 0
+    o.layout = layout
+    o.autotune = 1 if autotune else 0
+    if m is not None:
+        o.krylov.m = m
+    if tol is not None:
+        o.krylov.tol = tol
+    raw, nrm, im = np.zeros(nt), np.zeros(nt), np.zeros(nt)
+    st = OtocStats()
+    dp = lambda a: a.ctypes.data_as(_dp)
+    _check(_lib.syk_green(ham.handle, n, float(beta), dp(t), nt, ct.byref(o), dp(raw), dp(nrm), dp(im),
+                          ct.byref(st), _stream(stream)))
+    return raw, nrm, im, {f: getattr(st, f) for f, _ in OtocStats._fields_}
+
+
+def otoc_batch(items, beta: float, t, nvec: int = 1, m: int = 30, tol: float = 1e-7, variant: int = -1,
+               max_substeps: int = 0, stream=None):
+    """Batched OTOC (syk_otoc_batch).  items: sequence of (N, k, seed, i, j, state_seed).
+    Returns (F_raw, F_norm, F_imag, stats) with arrays of shape (len(items), len(t))."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    nt = t.size
+    n = len(items)
+    arr = (BatchItem * n)(*[BatchItem(int(N), float(k), int(seed), int(i), int(j), int(ss))
+                            for (N, k, seed, i, j, ss) in items])
+    o = BatchOpts(nvec, float(beta), m, float(tol), variant, max_substeps)
+    raw, nrm, im = np.zeros((n, nt)), np.zeros((n, nt)), np.zeros((n, nt))
+    st = BatchStats()
+    dp = lambda a: a.ctypes.data_as(_dp)
+    _check(_lib.syk_otoc_batch(arr, n, dp(t), nt, ct.byref(o), dp(raw), dp(nrm), dp(im), ct.byref(st),
+                               _stream(stream)))
+    out = {f: getattr(st, f) for f, _ in BatchStats._fields_ if f != "tuned_ms"}
+    out["tuned_ms"] = list(st.tuned_ms)
+    return raw, nrm, im, out
+
+
 def workspace_bytes(N: int, m: int, dtype: int, nvec: int = 1) -> int:
     b = ct.c_uint64()
     _check(_lib.syk_workspace_bytes(N, m, dtype, nvec, ct.byref(b)))
@@ -318,6 +387,11 @@ def autotune(ham: Hamiltonian, dtype: int, stream=None):
     ms = (ct.c_float * 16)()
     _check(_lib.syk_autotune(ham.handle, dtype, ct.byref(v), ms, 16, _stream(stream)))
     return v.value, [round(float(t), 4) for t in ms if t != -1.0]
+
+
+def select_variant(ham: Hamiltonian, dtype: int, variant: int):
+    """Pin the tiled apply_H variant for this handle (tests, reproducible timings)."""
+    _check(_lib.syk_select_variant(ham.handle, dtype, variant))
 
 
 def kernel_revision() -> str:

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "apply_plan.hpp"
+#include "batch.hpp"
 #include "engine.hpp"
 #include "krylov.hpp"
 #include "otoc.hpp"
@@ -246,6 +247,58 @@ syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t
     });
 }
 
+syk_status syk_green(const syk_ham *h, int n, double beta, const double *t, int nt, const syk_otoc_opts *o,
+                     double *G_raw, double *G_norm, double *G_imag, syk_otoc_stats *stats, void *stream) {
+    return guarded([&] {
+        require(h && t && o, "NULL argument");
+        syk::check_otoc_args(h->h.N, n, -1, beta, t, nt, *o, syk::Correlator::Green);
+        check_device();
+        auto t0 = std::chrono::steady_clock::now();
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        syk_otoc_stats st{};
+        syk::otoc_compute(H, n, -1, beta, t, nt, *o, syk::thread_workspace(0), as_stream(stream), G_raw, G_norm,
+                          G_imag, st, nullptr, syk::Correlator::Green);
+        st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (stats) *stats = st;
+    });
+}
+
+syk_status syk_otoc_batch(const syk_batch_item *items, int n_items, const double *t, int nt,
+                          const syk_batch_opts *o, double *F_raw, double *F_norm, double *F_imag,
+                          syk_batch_stats *stats, void *stream) {
+    return guarded([&] {
+        require(items && t && o, "NULL argument");
+        require(n_items >= 1, "n_items must be >= 1");
+        require(o->nvec >= 1, "nvec must be >= 1");
+        require(std::isfinite(o->beta) && o->beta >= 0.0, "beta must be finite and >= 0");
+        require(o->m >= 2 && o->m <= syk::kMaxKrylov, "m must lie in [2, 60]");
+        require(o->tol > 0.0 && std::isfinite(o->tol), "tol must be positive");
+        require(o->variant >= -1 && o->variant < static_cast<int>(syk::batch_variants().size()),
+                "variant must be -1 or a launch shape index");
+        require(o->max_substeps >= 0, "max_substeps must be >= 0");
+        require(nt >= 1, "nt must be >= 1");
+        for (int k = 0; k < nt; ++k) {
+            require(std::isfinite(t[k]) && t[k] >= 0.0, "t must be finite and >= 0");
+            if (k) require(t[k] >= t[k - 1], "t must be non-decreasing");
+        }
+        for (int r = 0; r < n_items; ++r) {
+            const syk_batch_item &it = items[r];
+            check_N(it.N);
+            require(it.N / 2 - 1 >= 8 && it.N / 2 - 1 <= 15, "batched items need 18 <= N <= 32");
+            require(std::isfinite(it.k) && it.k > 0.0, "k must be positive");
+            const double K = std::floor(it.k * it.N + 0.5);
+            require(K >= 1.0 && K <= it.N * (it.N - 1.0) * (it.N - 2.0) * (it.N - 3.0) / 24.0,
+                    "K = round(k N) must lie in [1, C(N,4)]");
+            require(it.i >= 0 && it.i < it.N && it.j >= 0 && it.j < it.N && it.i != it.j,
+                    "Majorana indices must be distinct and in [0, N)");
+        }
+        check_device();
+        syk_batch_stats st{};
+        syk::otoc_batch(items, n_items, t, nt, *o, F_raw, F_norm, F_imag, st, as_stream(stream));
+        if (stats) *stats = st;
+    });
+}
+
 syk_status syk_engine_create(const syk_engine_opts *o, syk_engine **out) {
     return guarded([&] {
         require(out != nullptr, "out is NULL");
@@ -350,7 +403,8 @@ syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int 
         out->tile_bits = bt;
         out->variant = var;
         const int rot = layout >= 0 ? layout : (c64 ? H.internal_rotation<float>(var) : H.internal_rotation<double>(var));
-        const syk::HostPlan hp = syk::build_host_plan(H.block_terms[blk], H.L, bt, rb, tv.nbuf, tv.pf, rot, c64 ? 8u : 16u);
+        const syk::HostPlan hp = syk::build_host_plan(H.block_terms[blk], H.L, bt, rb, tv.nbuf, tv.pf, rot, c64 ? 8u : 16u,
+                                                      syk::resident_bits(tv));
         // consistency: the tile map is a bijection and every term sits in one group
         std::vector<char> seen(hp.n_tiles, 0);
         for (uint32_t t : hp.tile_map) {
@@ -362,8 +416,9 @@ syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int 
         int real_groups = 0;
         for (int g = 0; g < hp.n_groups; ++g) real_groups += hp.grp_first[g + 1] > hp.grp_first[g];
         out->n_groups = real_groups;
-        out->classes5 = hp.classes5;
-        out->classes8 = hp.classes8;
+        out->classes_xcd = hp.classes_xcd;
+        out->classes_gpu = hp.classes_gpu;
+        out->res_bits = hp.res_bits;
         out->n_tiles = hp.n_tiles;
     });
 }
@@ -392,6 +447,21 @@ syk_status syk_autotune(const syk_ham *h, syk_dtype dt, int *variant, float *ms,
     });
 }
 
+syk_status syk_select_variant(const syk_ham *h, syk_dtype dt, int variant) {
+    return guarded([&] {
+        require(h != nullptr, "NULL handle");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        const int nv = (dt == SYK_C64) ? static_cast<int>(syk::tiled_variants<float>().size())
+                                       : static_cast<int>(syk::tiled_variants<double>().size());
+        require(variant >= 0 && variant < nv, "variant out of range (see syk_autotune's ms array)");
+        int dev = 0;
+        SYK_HIP(hipGetDevice(&dev));
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        std::lock_guard<std::mutex> g(H.dev_mu);
+        H.tuned[{dt == SYK_C128 ? 1 : 0, dev}] = variant;
+    });
+}
+
 syk_status syk_release_workspace(void) {
     return guarded([&] {
         check_device();
@@ -417,6 +487,6 @@ const char *syk_status_string(syk_status s) {
 
 const char *syk_last_error(void) { return g_last_error.c_str(); }
 
-const char *syk_kernel_revision(void) { return "tiled-dma-5"; }
+const char *syk_kernel_revision(void) { return "tiled-dma-6"; }
 
 }  // extern "C"

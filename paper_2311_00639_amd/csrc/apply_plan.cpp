@@ -4,14 +4,16 @@
 //  * layout rotation s: amplitude index bit b holds qubit (b + s) mod L, so the 2^BT
 //    amplitudes of a tile are the qubits [s, s + BT) (mod L).  Only the vector layout
 //    changes: masks are rotated the same way, so XOR/AND/parity arithmetic is unchanged.
-//  * subspaces W5 (5 dims) and W8 (8 dims) of the tile-index space: the tiles resident on
-//    one XCD at the same time form a coset of W5, those resident on the whole GPU a coset
-//    of W8 (workgroups are dispatched round-robin over the 8 XCDs).  Partner tiles of two
-//    groups g, g' coincide across resident workgroups iff g ^ g' lies in the subspace, so
-//    the subspaces are grown greedily from the most frequent differences of partner
-//    offsets, and groups are visited class by class.
+//  * subspaces Wx (r dims, r = 5 + log2 of the workgroups resident per CU) and Wg (r + 3
+//    dims) of the tile-index space: the 2^r tiles resident on one XCD at the same time
+//    form a coset of Wx, those resident on the whole GPU a coset of Wg (workgroups are
+//    dispatched round-robin over the 8 XCDs).  Partner tiles of two groups g, g' coincide
+//    across resident workgroups iff g ^ g' lies in the subspace, so the subspaces are
+//    grown greedily from the most frequent differences of partner offsets, and groups are
+//    visited class by class.
 //  * cost model: L2 requests scale with the number of groups D, L2 misses with the number
-//    of classes modulo W5; the rotation minimising D + 2 * classes is taken.
+//    of classes modulo Wx; the rotation minimising D + 2 * classes_x + classes_g / 2 is
+//    taken.
 #include <algorithm>
 #include <map>
 #include <numeric>
@@ -110,12 +112,12 @@ std::vector<uint32_t> grow(const std::vector<uint32_t> &G, Echelon &E, int dims,
 struct Candidate {
     int s = 0;
     std::vector<uint32_t> G;
-    std::vector<uint32_t> w5, w8;     // basis vectors picked (w8 extends w5)
-    int D = 0, c5 = 0, c8 = 0;
+    std::vector<uint32_t> wx, wg;     // basis vectors picked (wg extends wx)
+    int D = 0, cx = 0, cg = 0;
     double cost = 0;
 };
 
-Candidate evaluate(const std::vector<BlockTerm> &terms, int L, int bt, int s) {
+Candidate evaluate(const std::vector<BlockTerm> &terms, int L, int bt, int s, int res_bits) {
     Candidate c;
     c.s = s;
     const int tb = L - bt;
@@ -124,17 +126,17 @@ Candidate evaluate(const std::vector<BlockTerm> &terms, int L, int bt, int s) {
     c.G.erase(std::unique(c.G.begin(), c.G.end()), c.G.end());
     c.D = static_cast<int>(c.G.size());
     Echelon E;
-    c.w5 = grow(c.G, E, 5, tb);
-    c.c5 = count_classes(c.G, E);
-    c.w8 = grow(c.G, E, 3, tb);
-    c.c8 = count_classes(c.G, E);
-    c.cost = c.D + 2.0 * c.c5 + 0.5 * c.c8;
+    c.wx = grow(c.G, E, res_bits, tb);
+    c.cx = count_classes(c.G, E);
+    c.wg = grow(c.G, E, 3, tb);
+    c.cg = count_classes(c.G, E);
+    c.cost = c.D + 2.0 * c.cx + 0.5 * c.cg;
     return c;
 }
 
 }  // namespace
 
-int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt) {
+int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt, int res_bits) {
     if (L <= bt) return 0;
     // pre-select by the group count alone, then score the best few in full
     std::vector<std::pair<int, int>> byD;
@@ -148,7 +150,7 @@ int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt) {
     int best_s = 0;
     double best = 1e300;
     for (size_t i = 0; i < byD.size() && i < 4; ++i) {
-        const Candidate c = evaluate(terms, L, bt, byD[i].second);
+        const Candidate c = evaluate(terms, L, bt, byD[i].second, res_bits);
         if (c.cost < best) {
             best = c.cost;
             best_s = c.s;
@@ -158,25 +160,26 @@ int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt) {
 }
 
 HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int rb, int mult, int extra, int s,
-                         uint32_t elem_bytes) {
+                         uint32_t elem_bytes, int res_bits) {
     HostPlan hp;
     hp.rot = s;
     const int tbits = L - bt;
     hp.n_tiles = 1u << tbits;
-    const Candidate c = evaluate(terms, L, bt, s);
+    hp.res_bits = res_bits;
+    const Candidate c = evaluate(terms, L, bt, s, res_bits);
     hp.D = c.D;
-    hp.classes5 = c.c5;
-    hp.classes8 = c.c8;
+    hp.classes_xcd = c.cx;
+    hp.classes_gpu = c.cg;
 
-    // basis of the tile-index space: W8 extension (blockIdx bits [0,3): the XCD), W5
-    // (bits [3,8): XCD-local), then unit vectors completing it; blockIdx bit i selects
+    // basis of the tile-index space: Wg extension (blockIdx bits [0,3): the XCD), Wx
+    // (bits [3, 3 + r): XCD-local), then unit vectors completing it; blockIdx bit i selects
     // basis vector i, so the map is a bijection
     std::vector<uint32_t> basis;
     {
         Echelon E;
         std::vector<uint32_t> order;
-        for (uint32_t v : c.w8) order.push_back(v);
-        for (uint32_t v : c.w5) order.push_back(v);
+        for (uint32_t v : c.wg) order.push_back(v);
+        for (uint32_t v : c.wx) order.push_back(v);
         for (int bit = 0; bit < tbits; ++bit) order.push_back(1u << bit);
         for (uint32_t v : order)
             if (E.add(v)) basis.push_back(v);
@@ -190,13 +193,13 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
         hp.tile_map[b] = t;
     }
 
-    // group order: by class modulo W8, then modulo W5, then offset
+    // group order: by class modulo Wg, then modulo Wx, then offset
     Echelon E5, E8;
-    for (uint32_t v : c.w5) {
+    for (uint32_t v : c.wx) {
         E5.add(v);
         E8.add(v);
     }
-    for (uint32_t v : c.w8) E8.add(v);
+    for (uint32_t v : c.wg) E8.add(v);
     const uint32_t low = (1u << bt) - 1u;
     const int tb = bt - rb;
     const uint32_t tmask = (1u << tb) - 1u;

@@ -112,11 +112,14 @@ __device__ __forceinline__ V *pick(V *b0, V *b1, V *b2, V *b3) {
 
 // Partner tiles stream into NBUF LDS buffers by direct loads, NBUF - 1 of them in flight
 // while the current one is consumed; the buffers are distinct LDS objects so that reads
-// of one need not wait for copies into the others.  n_groups is a multiple of NBUF (the
-// host pads with empty groups) and grp_g holds NBUF - 1 extra entries.  blockIdx maps to
-// an output tile through tile_map.
-template <typename T, int BT, int RB, int NBUF>
-__global__ void __launch_bounds__(1 << (BT - RB)) apply_h_tiled(
+// of one need not wait for copies into the others.  With NBUF = 1 the copy and the
+// compute of a group alternate inside the workgroup and OCC workgroups share a CU, so one
+// computes while another waits for its tile.  n_groups is a multiple of NBUF (the host
+// pads with empty groups) and grp_g holds NBUF - 1 extra entries.  blockIdx maps to an
+// output tile through tile_map.  The second launch bound (waves per SIMD) keeps OCC
+// workgroups resident.
+template <typename T, int BT, int RB, int NBUF, int OCC>
+__global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) apply_h_tiled(
     const typename V2t<T>::type *__restrict__ x, typename V2t<T>::type *__restrict__ y, uint64_t ld,
     const uint32_t *__restrict__ tile_map, const uint32_t *__restrict__ grp_g,
     const uint32_t *__restrict__ grp_first, const uint32_t *__restrict__ grp_mid, int n_groups,
@@ -126,9 +129,9 @@ __global__ void __launch_bounds__(1 << (BT - RB)) apply_h_tiled(
     constexpr int R = 1 << RB;
     constexpr int TILE = 1 << BT;
     constexpr int PER = TILE * 2 * static_cast<int>(sizeof(T)) / (NT * 16);
-    static_assert(NBUF >= 2 && NBUF <= 4, "2 to 4 LDS buffers");
+    static_assert(NBUF >= 1 && NBUF <= 4, "1 to 4 LDS buffers");
     __shared__ V b0[TILE];
-    __shared__ V b1[TILE];
+    __shared__ V b1[NBUF > 1 ? TILE : 1];
     __shared__ V b2[NBUF > 2 ? TILE : 1];
     __shared__ V b3[NBUF > 3 ? TILE : 1];
 
@@ -143,33 +146,52 @@ __global__ void __launch_bounds__(1 << (BT - RB)) apply_h_tiled(
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = V{T(0), T(0)};
 
-    dma_tile<T, BT, RB>(partner(0), b0, tid);
-    if constexpr (NBUF > 2) dma_tile<T, BT, RB>(partner(1), b1, tid);
-    if constexpr (NBUF > 3) dma_tile<T, BT, RB>(partner(2), b2, tid);
-    for (int g0 = 0; g0 < n_groups; g0 += NBUF) {
-        auto step = [&](auto kc) {
-            constexpr int K = decltype(kc)::value;
-            const int gi = g0 + K;
-            // this group's copy was issued NBUF - 1 steps ago; NBUF - 2 copies are newer.
-            // A bare s_barrier (no fence): each wave has waited for its own pieces of the
-            // tile, LDS is coherent within the CU, and the barrier also guarantees that
-            // every wave is done reading the buffer the next copy overwrites.
-            __builtin_amdgcn_s_waitcnt(waitcnt_vm(PER * (NBUF - 2)));
-            asm volatile("" ::: "memory");   // no LDS access or copy moves across the barrier
+    if constexpr (NBUF == 1) {
+        for (int gi = 0; gi < n_groups; ++gi) {
+            // the previous group's reads of b0 ended at the barrier closing its step
+            dma_tile<T, BT, RB>(partner(gi), b0, tid);
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            asm volatile("" ::: "memory");
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
-            dma_tile<T, BT, RB>(partner(gi + NBUF - 1), pick<(K + NBUF - 1) % NBUF>(b0, b1, b2, b3), tid);
-            const V *b = pick<K>(b0, b1, b2, b3);
             const int t0 = static_cast<int>(grp_first[gi]);
             const int tm = static_cast<int>(grp_mid[gi]);
             const int t1 = static_cast<int>(grp_first[gi + 1]);
-            apply_terms<T, BT, RB, false>(acc, b, recs, coef, t0, tm, tile, tid);
-            apply_terms<T, BT, RB, true>(acc, b, recs, coef, tm, t1, tile, tid);
-        };
-        step(std::integral_constant<int, 0>{});
-        step(std::integral_constant<int, 1>{});
-        if constexpr (NBUF > 2) step(std::integral_constant<int, 2>{});
-        if constexpr (NBUF > 3) step(std::integral_constant<int, 3>{});
+            apply_terms<T, BT, RB, false>(acc, b0, recs, coef, t0, tm, tile, tid);
+            apply_terms<T, BT, RB, true>(acc, b0, recs, coef, tm, t1, tile, tid);
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+        }
+    } else {
+        dma_tile<T, BT, RB>(partner(0), b0, tid);
+        if constexpr (NBUF > 2) dma_tile<T, BT, RB>(partner(1), b1, tid);
+        if constexpr (NBUF > 3) dma_tile<T, BT, RB>(partner(2), b2, tid);
+        for (int g0 = 0; g0 < n_groups; g0 += NBUF) {
+            auto step = [&](auto kc) {
+                constexpr int K = decltype(kc)::value;
+                const int gi = g0 + K;
+                // this group's copy was issued NBUF - 1 steps ago; NBUF - 2 copies are newer.
+                // A bare s_barrier (no fence): each wave has waited for its own pieces of the
+                // tile, LDS is coherent within the CU, and the barrier also guarantees that
+                // every wave is done reading the buffer the next copy overwrites.
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(PER * (NBUF - 2)));
+                asm volatile("" ::: "memory");   // no LDS access or copy moves across the barrier
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
+                dma_tile<T, BT, RB>(partner(gi + NBUF - 1), pick<(K + NBUF - 1) % NBUF>(b0, b1, b2, b3), tid);
+                const V *b = pick<K>(b0, b1, b2, b3);
+                const int t0 = static_cast<int>(grp_first[gi]);
+                const int tm = static_cast<int>(grp_mid[gi]);
+                const int t1 = static_cast<int>(grp_first[gi + 1]);
+                apply_terms<T, BT, RB, false>(acc, b, recs, coef, t0, tm, tile, tid);
+                apply_terms<T, BT, RB, true>(acc, b, recs, coef, tm, t1, tile, tid);
+            };
+            step(std::integral_constant<int, 0>{});
+            step(std::integral_constant<int, 1>{});
+            if constexpr (NBUF > 2) step(std::integral_constant<int, 2>{});
+            if constexpr (NBUF > 3) step(std::integral_constant<int, 3>{});
+        }
     }
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));      // no copy may still target LDS at exit
     V *dst = yv + (static_cast<uint64_t>(tile) << BT);
@@ -188,22 +210,31 @@ __global__ void __launch_bounds__(1 << (BT - RB)) apply_h_tiled(
     const V *vp = reinterpret_cast<const V *>(lf.vprev) + (static_cast<uint64_t>(tile) << BT);
     const V *vc = reinterpret_cast<const V *>(lf.vcur) + (static_cast<uint64_t>(tile) << BT);
     double sum[4] = {0.0, 0.0, 0.0, 0.0};
+    auto epilogue = [&](auto has_prev) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = r * NT + tid;
-        V w = acc[r];
-        if (lf.vprev) {
-            const V p = vp[i];
-            w.x -= bp * p.x;
-            w.y -= bp * p.y;
+        for (int r = 0; r < R; ++r) {
+            const int i = r * NT + tid;
+            V w = acc[r];
+            if constexpr (decltype(has_prev)::value) {
+                const V p = vp[i];
+                w.x -= bp * p.x;
+                w.y -= bp * p.y;
+            }
+            const V c = vc[i];
+            dst[i] = w;
+            sum[0] += static_cast<double>(c.x) * w.x + static_cast<double>(c.y) * w.y;
+            sum[1] += static_cast<double>(c.x) * w.y - static_cast<double>(c.y) * w.x;
+            sum[2] += static_cast<double>(w.x) * w.x + static_cast<double>(w.y) * w.y;
+            sum[3] += static_cast<double>(c.x) * c.x + static_cast<double>(c.y) * c.y;
+            // bound the loads in flight: with several workgroups per CU the register
+            // budget is 64 VGPRs
+            if (r % 2 == 1) __builtin_amdgcn_sched_barrier(0);
         }
-        const V c = vc[i];
-        dst[i] = w;
-        sum[0] += static_cast<double>(c.x) * w.x + static_cast<double>(c.y) * w.y;
-        sum[1] += static_cast<double>(c.x) * w.y - static_cast<double>(c.y) * w.x;
-        sum[2] += static_cast<double>(w.x) * w.x + static_cast<double>(w.y) * w.y;
-        sum[3] += static_cast<double>(c.x) * c.x + static_cast<double>(c.y) * c.y;
-    }
+    };
+    if (lf.vprev)
+        epilogue(std::true_type{});
+    else
+        epilogue(std::false_type{});
     __shared__ double red[4][NT / 64];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -221,7 +252,7 @@ __global__ void __launch_bounds__(1 << (BT - RB)) apply_h_tiled(
 
 }  // namespace
 
-template <typename T, int BT, int RB, int NBUF>
+template <typename T, int BT, int RB, int NBUF, int OCC>
 static void launch_variant(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_t ld, const LanczosFuse<T> &lf,
                            hipStream_t s) {
     using V = typename V2t<T>::type;
@@ -231,7 +262,7 @@ static void launch_variant(const ApplyPlan &pl, const T *x, T *y, int nvec, uint
     else
         coef = pl.c64;
     dim3 grid(pl.n_tiles, nvec);
-    hipLaunchKernelGGL((apply_h_tiled<T, BT, RB, NBUF>), grid, dim3(1 << (BT - RB)), 0, s,
+    hipLaunchKernelGGL((apply_h_tiled<T, BT, RB, NBUF, OCC>), grid, dim3(1 << (BT - RB)), 0, s,
                        reinterpret_cast<const V *>(x), reinterpret_cast<V *>(y), ld, pl.tile_map, pl.grp_g,
                        pl.grp_first, pl.grp_mid, pl.n_groups,
                        reinterpret_cast<const TermRec<1 << RB> *>(pl.meta), coef, lf);
@@ -244,21 +275,25 @@ void launch_apply_tiled(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_
     const TiledVariant &v = tiled_variants<T>()[pl.variant];
     const LanczosFuse<T> none{};
     if (lf && nvec != 1) fail(SYK_EDEVICE, "the fused Lanczos epilogue takes one vector");
-#define SYK_TV(BT, RB, NB)                                                      \
-    if (v.bt == BT && v.rb == RB && v.nbuf == NB) {                             \
-        launch_variant<T, BT, RB, NB>(pl, x, y, nvec, ld, lf ? *lf : none, s);  \
-        return;                                                                 \
+#define SYK_TV(BT, RB, NB, OC)                                                      \
+    if (v.bt == BT && v.rb == RB && v.nbuf == NB && v.occ == OC) {                  \
+        launch_variant<T, BT, RB, NB, OC>(pl, x, y, nvec, ld, lf ? *lf : none, s);  \
+        return;                                                                     \
     }
     if constexpr (sizeof(T) == 4) {
-        SYK_TV(13, 3, 2)
-        SYK_TV(12, 3, 2)
-        SYK_TV(12, 2, 4)
-        SYK_TV(11, 2, 2)
+        SYK_TV(13, 3, 2, 1)
+        SYK_TV(13, 3, 1, 2)
+        SYK_TV(12, 3, 1, 4)
+        SYK_TV(12, 3, 2, 2)
+        SYK_TV(12, 2, 4, 1)
+        SYK_TV(11, 2, 2, 4)
     } else {
-        SYK_TV(12, 2, 2)
-        SYK_TV(11, 2, 2)
-        SYK_TV(11, 1, 4)
-        SYK_TV(10, 1, 2)
+        SYK_TV(12, 2, 2, 1)
+        SYK_TV(12, 2, 1, 2)
+        SYK_TV(11, 2, 1, 4)
+        SYK_TV(11, 2, 2, 2)
+        SYK_TV(11, 1, 4, 1)
+        SYK_TV(10, 1, 2, 4)
     }
 #undef SYK_TV
     fail(SYK_EDEVICE, "unknown tiled apply_H variant");

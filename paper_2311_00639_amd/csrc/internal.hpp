@@ -48,9 +48,14 @@ struct DeviceTables {            // per device, per block: real terms first, the
 // 2^rb register-held outputs per thread (2^(bt-rb) threads per workgroup), nbuf LDS
 // buffers of one partner tile each (at most 128 KiB of the 160 KiB per CU), pf = nbuf - 1
 // partner tiles in flight.  The autotuner times them on the actual Hamiltonian.
+// Compiled variant of the tiled apply_H kernel: tiles of 2^bt amplitudes, 2^rb per
+// thread, nbuf LDS partner buffers (nbuf - 1 copies in flight; 1 = copy, then compute),
+// pf extra partner entries at the end of the group list, occ workgroups resident per CU
+// (the planner's XCD-resident subspace has dimension 5 + log2(occ)).
 struct TiledVariant {
-    int bt, rb, nbuf, pf;
+    int bt, rb, nbuf, pf, occ;
 };
+inline int resident_bits(const TiledVariant &v) { return 5 + (v.occ >= 4 ? 2 : v.occ >= 2 ? 1 : 0); }
 template <typename T>
 const std::vector<TiledVariant> &tiled_variants();
 // variant used before (or without) autotuning

@@ -1,4 +1,5 @@
-// Regularised OTOC of Eq. (2) by the random-state estimator of the supplement, computed as
+// Regularised OTOC of Eq. (2) and the Green function of the supplement, by the
+// random-state estimator of the supplement.  The OTOC is computed as
 // the sum of the U-block and D-block chains ("+ swap UD"):
 //
 //   F_v(t) = <psi| e^{(it-b/8)H} W e^{-(it+b/4)H} V e^{(it-b/4)H} W e^{-(it+b/4)H} V e^{-bH/8} |psi>
@@ -47,7 +48,7 @@ void apply_gamma(int N, int n, int src, int rot, const T *x, T *y, uint64_t amps
 template <typename T>
 void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<double> &ts, const syk_otoc_opts &o,
               std::vector<std::complex<double>> &F, syk_otoc_stats &st, char *ws, hipStream_t s,
-              const std::atomic<int> *cancel) {
+              const std::atomic<int> *cancel, Correlator kind) {
     const uint64_t n = 1ULL << h.L;
     const size_t vb = up(static_cast<size_t>(n) * 2 * sizeof(T));
     T *l = reinterpret_cast<T *>(ws);
@@ -77,8 +78,22 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
         st.substeps += ks.substeps;
         st.max_err_est = std::max(st.max_err_est, ks.err_est);
     };
+    // <a, b> over the block, reduced in double on the device, read back (synchronises)
+    auto overlap = [&](const T *a, const T *b) {
+        launch_dot_partials<T>(a, b, n, kr[0].partials(), kr[0].n_part(), s);
+        launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 2, kr[0].scratch(), s);
+        SYK_HIP(hipMemcpyAsync(hd.data(), kr[0].scratch(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        SYK_HIP(hipStreamSynchronize(s));
+        if (!std::isfinite(hd[0]) || !std::isfinite(hd[1])) fail(SYK_ENUMERIC, "non-finite overlap");
+        return cd(hd[0], hd[1]);
+    };
     int done = 0;
     const int total = o.nvec * 2 * nt;
+    auto point_done = [&]() {
+        ++done;
+        if (o.progress) o.progress(o.progress_ctx, done, total);
+        if (cancel && cancel->load()) fail(SYK_ECANCELLED, "request cancelled");
+    };
     for (int v = 0; v < o.nvec; ++v) {
         for (int A = 0; A < 2; ++A) {
             const int B = 1 - A;
@@ -88,6 +103,25 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
             launch_haar_raw<T>(o.state_seed, v, h.L, rot, pu, pd, kr[0].partials(), kr[0].n_part(), s);
             launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 1, kr[0].scratch(), s);
             launch_scale_pair<T>(pu, pd, n, kr[0].scratch(), s);
+            if (kind == Correlator::Green) {
+                // G_A(t) = <psi_A| e^{(it-b/2)H_A} chi^{AB} e^{-itH_B} chi^{BA} e^{-bH_A/2} |psi_A>:
+                // l = e^{-itH_A} r0 and r2 = e^{-itH_B} chi^{BA} r0, both incremental in t
+                prop(A, cd(-beta / 2.0, 0.0), l);                 // l = r0
+                apply_gamma<T>(h.N, i, A, rot, l, r2, n, s);                 // gamma^{BA} r0
+                double tprev = 0.0;
+                for (int k = 0; k < nt; ++k) {
+                    const double dt = ts[k] - tprev;
+                    if (dt > 0.0) {
+                        prop(B, cd(0.0, -dt), r2);
+                        prop(A, cd(0.0, -dt), l);
+                    }
+                    tprev = ts[k];
+                    apply_gamma<T>(h.N, i, B, rot, r2, tmp, n, s);            // gamma^{AB} r2
+                    F[k] += 0.5 * overlap(l, tmp);             // (1/sqrt 2)^2 from chi = gamma / sqrt 2
+                    point_done();
+                }
+                continue;
+            }
             prop(A, cd(-beta / 8.0, 0.0), l);                     // l = r0
             apply_gamma<T>(h.N, j, A, rot, l, r2, n, s);                // V_BA r0
             prop(B, cd(-beta / 4.0, 0.0), r2);                     // r2
@@ -105,15 +139,8 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
                 apply_gamma<T>(h.N, j, A, rot, r4, tmp, n, s);          // V_BA r4
                 prop(B, cd(-beta / 4.0, -t), tmp);                 // r6
                 apply_gamma<T>(h.N, i, B, rot, tmp, r4, n, s);          // W_AB r6
-                launch_dot_partials<T>(l, r4, n, kr[0].partials(), kr[0].n_part(), s);
-                launch_reduce_partials(kr[0].partials(), kr[0].n_part(), 2, kr[0].scratch(), s);
-                SYK_HIP(hipMemcpyAsync(hd.data(), kr[0].scratch(), 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-                SYK_HIP(hipStreamSynchronize(s));
-                if (!std::isfinite(hd[0]) || !std::isfinite(hd[1])) fail(SYK_ENUMERIC, "non-finite OTOC overlap");
-                F[k] += 0.25 * cd(hd[0], hd[1]);
-                ++done;
-                if (o.progress) o.progress(o.progress_ctx, done, total);
-                if (cancel && cancel->load()) fail(SYK_ECANCELLED, "request cancelled");
+                F[k] += 0.25 * overlap(l, r4);
+                point_done();
             }
         }
     }
@@ -126,17 +153,21 @@ void otoc_run(Hamiltonian &h, int i, int j, double beta, const std::vector<doubl
 
 template void otoc_run<float>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
                               std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t,
-                              const std::atomic<int> *);
+                              const std::atomic<int> *, Correlator);
 template void otoc_run<double>(Hamiltonian &, int, int, double, const std::vector<double> &, const syk_otoc_opts &,
                                std::vector<std::complex<double>> &, syk_otoc_stats &, char *, hipStream_t,
-                               const std::atomic<int> *);
+                               const std::atomic<int> *, Correlator);
 
-void check_otoc_args(int N, int i, int j, double beta, const double *t, int nt, const syk_otoc_opts &o) {
+void check_otoc_args(int N, int i, int j, double beta, const double *t, int nt, const syk_otoc_opts &o,
+                     Correlator kind) {
     auto require = [](bool c, const char *msg) {
         if (!c) fail(SYK_EINVAL, msg);
     };
     require(t != nullptr, "NULL argument");
-    require(i >= 0 && i < N && j >= 0 && j < N && i != j, "Majorana indices must be distinct and in [0, N)");
+    if (kind == Correlator::Green)
+        require(i >= 0 && i < N, "Majorana index must lie in [0, N)");
+    else
+        require(i >= 0 && i < N && j >= 0 && j < N && i != j, "Majorana indices must be distinct and in [0, N)");
     require(nt >= 1, "nt must be >= 1");
     require(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
     require(o.nvec >= 1, "nvec must be >= 1");
@@ -152,7 +183,7 @@ void check_otoc_args(int N, int i, int j, double beta, const double *t, int nt, 
 
 void otoc_compute(Hamiltonian &H, int i, int j, double beta, const double *t, int nt, const syk_otoc_opts &o,
                   DeviceBuffer &ws, hipStream_t s, double *F_raw, double *F_norm, double *F_imag,
-                  syk_otoc_stats &st, const std::atomic<int> *cancel) {
+                  syk_otoc_stats &st, const std::atomic<int> *cancel, Correlator kind) {
     std::vector<double> ts(t, t + nt);
     const bool prepend = ts[0] != 0.0;
     if (prepend) ts.insert(ts.begin(), 0.0);
@@ -160,10 +191,10 @@ void otoc_compute(Hamiltonian &H, int i, int j, double beta, const double *t, in
     std::vector<std::complex<double>> F;
     if (o.dtype == SYK_C64) {
         ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(float)));
-        otoc_run<float>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel);
+        otoc_run<float>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel, kind);
     } else {
         ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(double)));
-        otoc_run<double>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel);
+        otoc_run<double>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel, kind);
     }
     const double f0 = F[0].real();
     const int off = prepend ? 1 : 0;

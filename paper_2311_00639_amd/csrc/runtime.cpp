@@ -65,12 +65,14 @@ const DeviceTables &Hamiltonian::tables(int blk) {
 
 template <>
 const std::vector<TiledVariant> &tiled_variants<float>() {
-    static const std::vector<TiledVariant> v = {{13, 3, 2, 1}, {12, 3, 2, 1}, {12, 2, 4, 3}, {11, 2, 2, 1}};
+    static const std::vector<TiledVariant> v = {{13, 3, 2, 1, 1}, {13, 3, 1, 0, 2}, {12, 3, 1, 0, 4},
+                                                {12, 3, 2, 1, 2}, {12, 2, 4, 3, 1}, {11, 2, 2, 1, 4}};
     return v;
 }
 template <>
 const std::vector<TiledVariant> &tiled_variants<double>() {
-    static const std::vector<TiledVariant> v = {{12, 2, 2, 1}, {11, 2, 2, 1}, {11, 1, 4, 3}, {10, 1, 2, 1}};
+    static const std::vector<TiledVariant> v = {{12, 2, 2, 1, 1}, {12, 2, 1, 0, 2}, {11, 2, 1, 0, 4},
+                                                {11, 2, 2, 1, 2}, {11, 1, 4, 3, 1}, {10, 1, 2, 1, 4}};
     return v;
 }
 template <>
@@ -87,7 +89,8 @@ const ApplyPlan &Hamiltonian::plan(int blk, int rot, int variant) {
     std::lock_guard<std::mutex> g(dev_mu);
     ApplyPlan &p = plans[std::make_tuple(blk, prec, d, rot, variant)];
     if (p.grp_g) return p;
-    HostPlan hp = build_host_plan(block_terms[blk], L, tv.bt, tv.rb, tv.nbuf, tv.pf, rot, 2 * sizeof(T));
+    HostPlan hp = build_host_plan(block_terms[blk], L, tv.bt, tv.rb, tv.nbuf, tv.pf, rot, 2 * sizeof(T),
+                                  resident_bits(tv));
     upload_plan(hp, tv.bt, tv.rb, p);
     p.variant = variant;
     return p;
@@ -101,7 +104,8 @@ int Hamiltonian::internal_rotation(int variant) {
     const int prec = sizeof(T) == 8 ? 1 : 0;
     std::lock_guard<std::mutex> g(dev_mu);
     int &r = rotation[prec][variant];
-    if (r < 0) r = choose_rotation(block_terms[0], L, tiled_variants<T>().at(variant).bt);
+    const TiledVariant &tv = tiled_variants<T>().at(variant);
+    if (r < 0) r = choose_rotation(block_terms[0], L, tv.bt, resident_bits(tv));
     return r;
 }
 template int Hamiltonian::internal_rotation<float>(int);

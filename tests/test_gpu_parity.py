@@ -100,9 +100,11 @@ def test_apply_h_repeatable_bitwise():
 
 
 # --------------------------------------------------------------------------- apply_H, large N
-def _sampled_rows_check(N, k, seed, dt, blk, nrows=3000):
+def _sampled_rows_check(N, k, seed, dt, blk, nrows=3000, variant=None):
     subs, J, _ = ensemble.sample_terms(N, k, seed)
     h = syk.create_hamiltonian(N, 4, k, seed)
+    if variant is not None:
+        syk.select_variant(h, dt, variant)
     n = 1 << (N // 2 - 1)
     x = inputs.complex_vector(n, seed + 1)[0]
     xd = dev(x, cdt(dt))
@@ -147,6 +149,39 @@ def test_apply_h_tiled_smallest_sizes(N, dt, blk):
         assert np.all(np.abs(y - yref) <= K * 2.0 ** -52 * mag)
     else:
         assert np.all(np.abs(y - yref) <= K * U24 * mag)
+
+
+N_VARIANTS = 6
+
+
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
+def test_every_tiled_variant(dt, variant):
+    """Each compiled tiled variant (tile size, LDS buffering, workgroups per CU), pinned:
+    sampled rows of apply_H against the oracle, and the fused Lanczos step against full
+    re-orthogonalisation with separate kernels."""
+    N = 40
+    y, yref, mag, K = _sampled_rows_check(N, 4, 400 + variant, dt, variant % 2, nrows=4000, variant=variant)
+    u = 2.0 ** -52 if dt == syk.C128 else U24
+    assert np.all(np.abs(y - yref) <= K * u * mag)
+    h = syk.create_hamiltonian(N, 4, 4, 400 + variant)
+    syk.select_variant(h, dt, variant)
+    n = 1 << (N // 2 - 1)
+    vd = dev(inputs.complex_vector(n, 50 + variant)[0], cdt(dt))
+    a = torch.empty_like(vd)
+    b = torch.empty_like(vd)
+    syk.krylov_expm(h, 0, 1.5j - 0.6, vd, a, m=30, reorth=0)
+    syk.krylov_expm(h, 0, 1.5j - 0.6, vd, b, m=30, reorth=2)
+    err = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
+    assert err <= (1e-10 if dt == syk.C128 else 2e-6)
+
+
+def test_select_variant_rejects_out_of_range():
+    h = syk.create_hamiltonian(40, 4, 4, 1)
+    with pytest.raises(syk.SykError):
+        syk.select_variant(h, syk.C64, N_VARIANTS)
+    n = len(syk.autotune(h, syk.C64)[1])
+    assert n == N_VARIANTS
 
 
 def test_apply_h_tiled_many_vectors_padded():

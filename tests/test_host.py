@@ -124,8 +124,8 @@ def test_plan_describe(N, k, dt):
     assert auto["tiled"] == 1 and std["tiled"] == 1
     L = N // 2 - 1
     assert auto["n_tiles"] == 1 << (L - auto["tile_bits"]) and 0 <= auto["rot"] < L
-    assert 1 <= auto["classes8"] <= auto["classes5"] <= auto["n_groups"] <= h.info()["K"]
-    cost = lambda d: d["n_groups"] + 2 * d["classes5"] + 0.5 * d["classes8"]
+    assert 1 <= auto["classes_gpu"] <= auto["classes_xcd"] <= auto["n_groups"] <= h.info()["K"]
+    cost = lambda d: d["n_groups"] + 2 * d["classes_xcd"] + 0.5 * d["classes_gpu"]
     assert cost(auto) <= cost(std) + 1e-9
     # the D block shares the x masks: same grouping
     assert syk.plan_describe(h, 1, dt, auto["rot"])["n_groups"] == auto["n_groups"]
@@ -134,3 +134,16 @@ def test_plan_describe(N, k, dt):
 def test_plan_describe_small_block_not_tiled():
     h = syk.create_hamiltonian(16, 4, 4, 1)
     assert syk.plan_describe(h, 0, syk.C64)["tiled"] == 0
+
+
+def test_batch_argument_checks_without_gpu():
+    """Argument errors of the batched call are reported before any device work."""
+    ts = [0.0, 1.0]
+    for items, kw in [([(34, 2, 1, 33, 32, 1)], {}), ([(24, 2, 1, 5, 5, 1)], {}), ([(24, 2, 1, 23, 22, 1)], {"m": 61}),
+                      ([(23, 2, 1, 22, 21, 1)], {}), ([(24, 2, 1, 23, 22, 1)], {"nvec": 0})]:
+        with pytest.raises(syk.SykError) as e:
+            syk.otoc_batch(items, 1.0, ts, **kw)
+        assert e.value.status == 1
+    with pytest.raises(syk.SykError) as e:
+        syk.otoc_batch([(24, 2, 1, 23, 22, 1)], 1.0, [1.0, 0.5])
+    assert e.value.status == 1
