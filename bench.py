@@ -20,6 +20,10 @@ Also reported, outside the timed region:
 * mixed_precision: the same realisation, Haar state and beta = 10 evaluated with
   complex128 states at t = 0, 5, 10, 20, and the complex64 curve's deviation from it
   there (the error of the mixed-precision path, per result);
+* batched: the persistent batched launch on a sample of the many-small-realisations
+  workload (realisations of N uniform in {24, 28, 32}, k uniform in {2, 4, 8}, seed
+  3000 + r, 4 Haar states each, complex64, beta = 10, t = 0:0.25:15, Krylov dim 30), with
+  realisations per hour;
 * serving: the request engine under a Poisson stream of OTOC requests (N uniform in
   {32, 36, 40, 44, 48}, k uniform in {1, 2, 4, 8}, beta = 10, t = 0:0.5:5, complex64,
   one Haar state, request seed 50000 + id) at a fixed offered rate for a fixed window,
@@ -47,7 +51,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
 # plain device copy of known size (profiles/apply_h_tiled_N56_k4_c64_traffic.txt).  Valid
 # only for the kernel revision it was measured on.
-TRAFFIC = {"kernel_rev": "tiled-dma-5", "fetch_bytes": 47161464021, "write_bytes": 1074283160}
+TRAFFIC = {"kernel_rev": "tiled-dma-6", "variant": 0, "fetch_bytes": 47161464021, "write_bytes": 1074283160}
 
 
 def t_grid():
@@ -94,13 +98,36 @@ def mixed_precision_check(syk, curve_c64, stream):
     ts = t_grid()
     idx = [ts.index(t) for t in t_check]
     c_raw, c_nrm, c_im = (curve_c64[0][idx], curve_c64[1][idx], curve_c64[2][idx])
+    scale = abs(float(raw[0]))
     return {"t": t_check, "F_norm_c128": [float(v) for v in nrm], "F_norm_c64": [float(v) for v in c_nrm],
+            "F_raw0_c128": float(raw[0]),
             "abs_err_F_norm": [float(abs(a - b)) for a, b in zip(c_nrm, nrm)],
-            "abs_err_F_raw": [float(abs(a - b)) for a, b in zip(c_raw, raw)],
-            "abs_err_F_imag": [float(abs(a - b)) for a, b in zip(c_im, im)],
-            "max_abs_err": float(max(max(abs(a - b) for a, b in zip(c_nrm, nrm)),
-                                     max(abs(a - b) for a, b in zip(c_raw, raw)))),
-            "tolerance": 1e-5, "c128_seconds": secs, "c128_matvecs": st["matvecs"]}
+            "rel_err_F_raw": [float(abs(a - b)) / scale for a, b in zip(c_raw, raw)],
+            "rel_err_F_imag": [float(abs(a - b)) / scale for a, b in zip(c_im, im)],
+            "max_abs_err_F_norm": float(max(abs(a - b) for a, b in zip(c_nrm, nrm))),
+            "tolerance_F_norm": 1e-5, "c128_seconds": secs, "c128_matvecs": st["matvecs"],
+            "note": "raw F carries the e^{-beta H} weights of an unnormalised state; errors of F_raw and F_imag "
+                    "are relative to |F_raw(0)|"}
+
+
+def batched_leg(syk, n_real=512, seed=3000):
+    """Persistent batched launch over n_real small-N realisations (4 Haar states each)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    items = []
+    for r in range(n_real):
+        n_maj = int(rng.choice([24, 28, 32]))
+        k = int(rng.choice([2, 4, 8]))
+        items.append((n_maj, k, seed + r, n_maj - 1, n_maj - 2, 100000 + r))
+    ts = [0.25 * n for n in range(61)]
+    t0 = time.perf_counter()
+    raw, nrm, im, st = syk.otoc_batch(items, 10.0, ts, nvec=4, m=30, tol=1e-7)
+    wall = time.perf_counter() - t0
+    return {"realisations": n_real, "vectors_per_realisation": 4, "jobs": st["n_jobs"], "wall_s": wall,
+            "kernel_s": st["kernel_ms"] / 1e3, "realisations_per_h": 3600.0 * n_real / wall,
+            "matvecs": st["matvecs"], "launch_shape": st["variant"], "tuned_ms": st["tuned_ms"],
+            "slots": st["slots"],
+            "mix": "N in {24,28,32}, k in {2,4,8}, seed 3000+r, 4 Haar states, c64, beta=10, t=0:0.25:15, m=30"}
 
 
 def serving_leg(syk, rate_hz=4.0, window_s=30.0, drain_s=60.0, seed=500):
@@ -153,6 +180,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -225,7 +253,7 @@ def main():
     term_amps_per_real = 3.0 * matvecs / args.steps * term_amps
     lib_rev = syk.kernel_revision()
     traffic = None
-    if TRAFFIC["fetch_bytes"] and TRAFFIC["kernel_rev"] == lib_rev:
+    if TRAFFIC["fetch_bytes"] and TRAFFIC["kernel_rev"] == lib_rev and TRAFFIC["variant"] == variant:
         traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
     rec = {
@@ -258,8 +286,15 @@ def main():
     }
     c10 = [r for b, r in results if b == 10.0]
     if not args.no_precision and c10:
+        print("[bench] complex128 reference points", file=sys.stderr, flush=True)
+        syk.release_workspace()
         rec["mixed_precision"] = mixed_precision_check(syk, c10[0], stream)
+        syk.release_workspace()
+    if not args.no_batched:
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        rec["batched"] = batched_leg(syk)
     if not args.no_serving:
+        print("[bench] serving leg", file=sys.stderr, flush=True)
         rec["serving"] = serving_leg(syk)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(term_amps_per_real)
