@@ -353,6 +353,8 @@ syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, doub
  * to workgroups so that the 2^res_bits tiles resident on one XCD form a coset of a
  * res_bits-dim subspace (classes_xcd = partner-tile classes modulo it, which sets the L2
  * misses) and those on the whole GPU one of a (res_bits + 3)-dim subspace (classes_gpu).
+ * A workgroup holds tiles_per_wg tiles (a coset of a small subspace chosen so that their
+ * partner tiles coincide as much as possible) and streams n_partners partner tiles.
  * rot is the vector layout: index bit b holds qubit (b + rot) mod L.  layout = -1 asks
  * for the planner's choice (the layout syk_otoc uses by default), layout >= 0 for that
  * rotation. */
@@ -360,6 +362,8 @@ typedef struct {
     int tiled;             /* 0: the block is served by the per-amplitude gather kernel */
     int variant;           /* compiled kernel variant in use (default or tuned) */
     int tile_bits, rot, n_groups, classes_xcd, classes_gpu, res_bits;
+    int tiles_per_wg;      /* output tiles a workgroup keeps in registers */
+    int n_partners;        /* partner tiles a workgroup streams (n_groups when tiles_per_wg = 1) */
     uint64_t n_tiles;
 } syk_plan_desc;
 syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, syk_plan_desc *out);
@@ -374,8 +378,8 @@ syk_status syk_autotune(const syk_ham *h, syk_dtype dt, int *variant, float *ms,
 
 /* Pin the tiled apply_H variant (0 <= variant < the number of entries syk_autotune
  * reports) for this handle, precision and the current device, in place of the default or
- * tuned one: for tests of every variant and for reproducible timings.  Host-only apart
- * from querying the current device.  Errors: EINVAL. */
+ * tuned one: for tests of every variant and for reproducible timings.  Host-only (without
+ * a device it applies to device 0, e.g. for syk_plan_describe).  Errors: EINVAL. */
 syk_status syk_select_variant(const syk_ham *h, syk_dtype dt, int variant);
 
 /* Release the library's cached device workspaces on the current device. */

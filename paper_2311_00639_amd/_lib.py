@@ -56,7 +56,7 @@ class PlanDesc(ct.Structure):
     _fields_ = [("tiled", ct.c_int), ("variant", ct.c_int), ("tile_bits", ct.c_int), ("rot", ct.c_int),
                 ("n_groups", ct.c_int),
                 ("classes_xcd", ct.c_int), ("classes_gpu", ct.c_int), ("res_bits", ct.c_int),
-                ("n_tiles", ct.c_uint64)]
+                ("tiles_per_wg", ct.c_int), ("n_partners", ct.c_int), ("n_tiles", ct.c_uint64)]
 
 
 class OtocStats(ct.Structure):

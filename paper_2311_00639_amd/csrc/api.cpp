@@ -404,18 +404,30 @@ syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int 
         out->variant = var;
         const int rot = layout >= 0 ? layout : (c64 ? H.internal_rotation<float>(var) : H.internal_rotation<double>(var));
         const syk::HostPlan hp = syk::build_host_plan(H.block_terms[blk], H.L, bt, rb, tv.nbuf, tv.pf, rot, c64 ? 8u : 16u,
-                                                      syk::resident_bits(tv));
-        // consistency: the tile map is a bijection and every term sits in one group
+                                                      syk::resident_bits(tv), tv.sr, tv.w);
+        // consistency: the workgroups' tiles cover the block once, and every (tile, term)
+        // pair is applied exactly once over the partner schedule
         std::vector<char> seen(hp.n_tiles, 0);
-        for (uint32_t t : hp.tile_map) {
-            if (t >= hp.n_tiles || seen[t]) syk::fail(SYK_EDEVICE, "tile map is not a bijection");
-            seen[t] = 1;
+        for (uint32_t t0 : hp.tile_map)
+            for (uint32_t h : hp.hvec) {
+                const uint32_t t = t0 ^ h;
+                if (t >= hp.n_tiles || seen[t]) syk::fail(SYK_EDEVICE, "tile map is not a bijection");
+                seen[t] = 1;
+            }
+        const size_t tpw = hp.hvec.size();
+        for (size_t i = 0; i < tpw; ++i) {
+            std::vector<int> hits(H.K, 0);
+            for (int st = 0; st < hp.n_pi; ++st) {
+                const uint32_t *r = &hp.ranges[(st * tpw + i) * 3];
+                for (uint32_t a = r[0]; a < r[2]; ++a) ++hits[a];
+            }
+            for (int a = 0; a < H.K; ++a)
+                if (hits[a] != 1) syk::fail(SYK_EDEVICE, "partner schedule does not apply every term once");
         }
-        if (hp.grp_first.back() != static_cast<uint32_t>(H.K)) syk::fail(SYK_EDEVICE, "groups do not cover all terms");
         out->rot = rot;
-        int real_groups = 0;
-        for (int g = 0; g < hp.n_groups; ++g) real_groups += hp.grp_first[g + 1] > hp.grp_first[g];
-        out->n_groups = real_groups;
+        out->n_groups = hp.D;
+        out->tiles_per_wg = static_cast<int>(tpw);
+        out->n_partners = hp.n_partners;
         out->classes_xcd = hp.classes_xcd;
         out->classes_gpu = hp.classes_gpu;
         out->res_bits = hp.res_bits;
@@ -455,7 +467,7 @@ syk_status syk_select_variant(const syk_ham *h, syk_dtype dt, int variant) {
                                        : static_cast<int>(syk::tiled_variants<double>().size());
         require(variant >= 0 && variant < nv, "variant out of range (see syk_autotune's ms array)");
         int dev = 0;
-        SYK_HIP(hipGetDevice(&dev));
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;     // host-only use: plans of device 0
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
         std::lock_guard<std::mutex> g(H.dev_mu);
         H.tuned[{dt == SYK_C128 ? 1 : 0, dev}] = variant;
@@ -487,6 +499,6 @@ const char *syk_status_string(syk_status s) {
 
 const char *syk_last_error(void) { return g_last_error.c_str(); }
 
-const char *syk_kernel_revision(void) { return "tiled-dma-6"; }
+const char *syk_kernel_revision(void) { return "tiled-multi-8"; }
 
 }  // extern "C"

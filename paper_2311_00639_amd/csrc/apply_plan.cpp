@@ -15,6 +15,7 @@
 //    of classes modulo Wx; the rotation minimising D + 2 * classes_x + classes_g / 2 is
 //    taken.
 #include <algorithm>
+#include <array>
 #include <map>
 #include <numeric>
 #include <tuple>
@@ -111,13 +112,71 @@ std::vector<uint32_t> grow(const std::vector<uint32_t> &G, Echelon &E, int dims,
 
 struct Candidate {
     int s = 0;
-    std::vector<uint32_t> G;
-    std::vector<uint32_t> wx, wg;     // basis vectors picked (wg extends wx)
+    std::vector<uint32_t> G;          // partner offsets of the term groups
+    std::vector<uint32_t> H;          // basis of the tiles a workgroup holds (relative offsets)
+    std::vector<uint32_t> Pi;         // partner offsets of a workgroup: G + span(H)
+    std::vector<uint32_t> wx, wg;     // resident subspaces (modulo span(H)); wg extends wx
     int D = 0, cx = 0, cg = 0;
     double cost = 0;
 };
 
-Candidate evaluate(const std::vector<BlockTerm> &terms, int L, int bt, int s, int res_bits) {
+std::vector<uint32_t> span_of(const std::vector<uint32_t> &basis) {
+    std::vector<uint32_t> sp{0u};
+    for (uint32_t v : basis) {
+        const size_t n = sp.size();
+        for (size_t i = 0; i < n; ++i) sp.push_back(sp[i] ^ v);
+    }
+    return sp;
+}
+
+std::vector<uint32_t> minkowski(const std::vector<uint32_t> &G, const std::vector<uint32_t> &sp) {
+    std::vector<uint32_t> out;
+    out.reserve(G.size() * sp.size());
+    for (uint32_t g : G)
+        for (uint32_t h : sp) out.push_back(g ^ h);
+    std::sort(out.begin(), out.end());
+    out.erase(std::unique(out.begin(), out.end()), out.end());
+    return out;
+}
+
+// w vectors chosen greedily among the most frequent differences of G so that G + span(H)
+// (the partner tiles of a workgroup holding the tiles t0 + span(H)) stays small
+std::vector<uint32_t> choose_h(const std::vector<uint32_t> &G, int w, int tb) {
+    std::vector<uint32_t> H;
+    if (w <= 0) return H;
+    std::unordered_map<uint32_t, int> freq;
+    for (size_t a = 0; a < G.size(); ++a)
+        for (size_t b = a + 1; b < G.size(); ++b) ++freq[G[a] ^ G[b]];
+    std::vector<std::pair<int, uint32_t>> cand;
+    for (const auto &kv : freq) cand.push_back({-kv.second, kv.first});
+    std::sort(cand.begin(), cand.end());
+    if (cand.size() > 60) cand.resize(60);
+    for (int d = 0; d < w; ++d) {
+        Echelon E;
+        for (uint32_t v : H) E.add(v);
+        uint32_t best = 0;
+        size_t best_n = ~static_cast<size_t>(0);
+        for (const auto &c : cand) {
+            if (!E.reduce(c.second)) continue;
+            std::vector<uint32_t> t = H;
+            t.push_back(c.second);
+            const size_t n = minkowski(G, span_of(t)).size();
+            if (n < best_n) {
+                best_n = n;
+                best = c.second;
+            }
+        }
+        if (!best) {      // no useful difference (e.g. a single group): any independent vector
+            for (int bit = 0; bit < tb && !best; ++bit)
+                if (E.reduce(1u << bit)) best = 1u << bit;
+        }
+        if (!best) break;
+        H.push_back(best);
+    }
+    return H;
+}
+
+Candidate evaluate(const std::vector<BlockTerm> &terms, int L, int bt, int s, int res_bits, int w) {
     Candidate c;
     c.s = s;
     const int tb = L - bt;
@@ -125,18 +184,21 @@ Candidate evaluate(const std::vector<BlockTerm> &terms, int L, int bt, int s, in
     std::sort(c.G.begin(), c.G.end());
     c.G.erase(std::unique(c.G.begin(), c.G.end()), c.G.end());
     c.D = static_cast<int>(c.G.size());
+    c.H = choose_h(c.G, std::min(w, tb), tb);
+    c.Pi = minkowski(c.G, span_of(c.H));
     Echelon E;
-    c.wx = grow(c.G, E, res_bits, tb);
-    c.cx = count_classes(c.G, E);
-    c.wg = grow(c.G, E, 3, tb);
-    c.cg = count_classes(c.G, E);
-    c.cost = c.D + 2.0 * c.cx + 0.5 * c.cg;
+    for (uint32_t v : c.H) E.add(v);
+    c.wx = grow(c.Pi, E, res_bits, tb);
+    c.cx = count_classes(c.Pi, E);
+    c.wg = grow(c.Pi, E, 3, tb);
+    c.cg = count_classes(c.Pi, E);
+    c.cost = static_cast<double>(c.Pi.size()) / (1 << c.H.size()) + 2.0 * c.cx + 0.5 * c.cg;
     return c;
 }
 
 }  // namespace
 
-int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt, int res_bits) {
+int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt, int res_bits, int w) {
     if (L <= bt) return 0;
     // pre-select by the group count alone, then score the best few in full
     std::vector<std::pair<int, int>> byD;
@@ -150,7 +212,7 @@ int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt, int res_
     int best_s = 0;
     double best = 1e300;
     for (size_t i = 0; i < byD.size() && i < 4; ++i) {
-        const Candidate c = evaluate(terms, L, bt, byD[i].second, res_bits);
+        const Candidate c = evaluate(terms, L, bt, byD[i].second, res_bits, w);
         if (c.cost < best) {
             best = c.cost;
             best_s = c.s;
@@ -160,23 +222,29 @@ int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt, int res_
 }
 
 HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int rb, int mult, int extra, int s,
-                         uint32_t elem_bytes, int res_bits) {
+                         uint32_t elem_bytes, int res_bits, int sr, int w) {
     HostPlan hp;
     hp.rot = s;
     const int tbits = L - bt;
     hp.n_tiles = 1u << tbits;
-    hp.res_bits = res_bits;
-    const Candidate c = evaluate(terms, L, bt, s, res_bits);
+    const Candidate c = evaluate(terms, L, bt, s, res_bits, w);
+    hp.w = static_cast<int>(c.H.size());
+    if (hp.w != w) fail(SYK_EDEVICE, "block too small for the tiles per workgroup of this variant");
+    hp.n_wg = hp.n_tiles >> hp.w;
+    hp.res_bits = res_bits + hp.w;
     hp.D = c.D;
+    hp.n_partners = static_cast<int>(c.Pi.size());
     hp.classes_xcd = c.cx;
     hp.classes_gpu = c.cg;
+    hp.hvec = span_of(c.H);
 
-    // basis of the tile-index space: Wg extension (blockIdx bits [0,3): the XCD), Wx
-    // (bits [3, 3 + r): XCD-local), then unit vectors completing it; blockIdx bit i selects
-    // basis vector i, so the map is a bijection
+    // workgroup index -> first tile t0: blockIdx bits [0,3) select the Wg extension (the
+    // XCD), bits [3, 3 + r) Wx (XCD-local), then vectors completing a basis of the tile
+    // space modulo span(H); the tiles t0 + span(H) of all workgroups cover it once
     std::vector<uint32_t> basis;
     {
         Echelon E;
+        for (uint32_t v : c.H) E.add(v);
         std::vector<uint32_t> order;
         for (uint32_t v : c.wg) order.push_back(v);
         for (uint32_t v : c.wx) order.push_back(v);
@@ -184,37 +252,28 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
         for (uint32_t v : order)
             if (E.add(v)) basis.push_back(v);
     }
-    if (static_cast<int>(basis.size()) != tbits) fail(SYK_EDEVICE, "tile basis construction failed");
-    hp.tile_map.resize(hp.n_tiles);
-    for (uint32_t b = 0; b < hp.n_tiles; ++b) {
+    if (static_cast<int>(basis.size()) != tbits - hp.w) fail(SYK_EDEVICE, "tile basis construction failed");
+    hp.tile_map.resize(hp.n_wg);
+    for (uint32_t b = 0; b < hp.n_wg; ++b) {
         uint32_t t = 0;
-        for (int i = 0; i < tbits; ++i)
+        for (int i = 0; i < tbits - hp.w; ++i)
             if ((b >> i) & 1u) t ^= basis[i];
         hp.tile_map[b] = t;
     }
 
-    // group order: by class modulo Wg, then modulo Wx, then offset
-    Echelon E5, E8;
-    for (uint32_t v : c.wx) {
-        E5.add(v);
-        E8.add(v);
-    }
-    for (uint32_t v : c.wg) E8.add(v);
+    // term records, grouped by partner offset g (real-phase terms, then i-phase terms)
     const uint32_t low = (1u << bt) - 1u;
     const int tb = bt - rb;
     const uint32_t tmask = (1u << tb) - 1u;
     const uint32_t rmask = (1u << rb) - 1u;
-    std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::vector<int>> by;
-    for (int a = 0; a < static_cast<int>(terms.size()); ++a) {
-        const uint32_t g = rotr_bits(terms[a].x, s, L) >> bt;
-        by[std::make_tuple(E8.reduce(g), E5.reduce(g), g)].push_back(a);
-    }
-    hp.grp_first.push_back(0);
+    std::map<uint32_t, std::vector<int>> byg;
+    for (int a = 0; a < static_cast<int>(terms.size()); ++a) byg[rotr_bits(terms[a].x, s, L) >> bt].push_back(a);
+    std::unordered_map<uint32_t, std::array<uint32_t, 3>> range;   // g -> (first, mid, end)
     uint32_t count = 0;
-    for (const auto &kv : by) {
-        hp.grp_g.push_back(std::get<2>(kv.first));
-        for (int pass = 0; pass < 2; ++pass) {          // real-phase terms, then i-phase terms
-            if (pass == 1) hp.grp_mid.push_back(count);
+    for (const auto &kv : byg) {
+        std::array<uint32_t, 3> r{count, 0u, 0u};
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) r[1] = count;
             for (int a : kv.second) {
                 const BlockTerm &t = terms[a];
                 if (t.imag != (pass == 1)) continue;
@@ -225,27 +284,56 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
                 hp.meta.push_back(xl & tmask);
                 hp.meta.push_back(z & tmask);
                 hp.meta.push_back(z >> bt);
-                hp.meta.push_back(0u);
-                for (uint32_t r = 0; r <= rmask; ++r)          // byte offset of partner register r ^ xr
-                    hp.meta.push_back(((r ^ xr) << tb) * elem_bytes);
-                for (uint32_t r = 0; r <= rmask; ++r)          // sign of output register r
-                    hp.meta.push_back((__builtin_popcount(r & zr) & 1) ? 0x80000000u : 0u);
+                if (sr) {
+                    hp.meta.push_back((xr << rb) | zr);        // code of the compiled register path
+                } else {
+                    hp.meta.push_back(0u);
+                    for (uint32_t q = 0; q <= rmask; ++q)      // byte offset of partner register q ^ xr
+                        hp.meta.push_back(((q ^ xr) << tb) * elem_bytes);
+                    for (uint32_t q = 0; q <= rmask; ++q)      // sign of output register q
+                        hp.meta.push_back((__builtin_popcount(q & zr) & 1) ? 0x80000000u : 0u);
+                }
                 hp.c.push_back(t.c);
                 ++count;
             }
         }
-        hp.grp_first.push_back(count);
+        r[2] = count;
+        range[kv.first] = r;
     }
-    const uint32_t last = hp.grp_g.empty() ? 0u : hp.grp_g.back();
-    while (hp.grp_g.empty() || hp.grp_g.size() % static_cast<size_t>(mult) != 0) {   // empty groups
-        hp.grp_g.push_back(last);
-        hp.grp_mid.push_back(count);
-        hp.grp_first.push_back(count);
-    }
-    hp.n_groups = static_cast<int>(hp.grp_g.size());
-    for (int k = 0; k < extra; ++k) hp.grp_g.push_back(last);   // targets of the last prefetches
-    hp.meta.resize(hp.meta.size() + 4 + 2 * (rmask + 1), 0u);   // one padding record (term prefetch)
+    hp.meta.resize(hp.meta.size() + (sr ? 4 : 4 + 2 * (rmask + 1)), 0u);   // one padding record (prefetch)
     hp.c.push_back(0.0);
+
+    // partner schedule: class by class modulo Wg, then Wx (both with span(H)), then offset
+    Echelon E5, E8;
+    for (uint32_t v : c.H) {
+        E5.add(v);
+        E8.add(v);
+    }
+    for (uint32_t v : c.wx) {
+        E5.add(v);
+        E8.add(v);
+    }
+    for (uint32_t v : c.wg) E8.add(v);
+    std::vector<std::tuple<uint32_t, uint32_t, uint32_t>> order;
+    for (uint32_t p : c.Pi) order.push_back(std::make_tuple(E8.reduce(p), E5.reduce(p), p));
+    std::sort(order.begin(), order.end());
+    const size_t tpw = hp.hvec.size();
+    for (const auto &o : order) {
+        const uint32_t p = std::get<2>(o);
+        hp.pi.push_back(p);
+        for (size_t i = 0; i < tpw; ++i) {
+            auto it = range.find(p ^ hp.hvec[i]);
+            const std::array<uint32_t, 3> r = it == range.end() ? std::array<uint32_t, 3>{0u, 0u, 0u} : it->second;
+            hp.ranges.insert(hp.ranges.end(), r.begin(), r.end());
+        }
+    }
+    const uint32_t last = hp.pi.empty() ? 0u : hp.pi.back();
+    while (hp.pi.empty() || hp.pi.size() % static_cast<size_t>(mult) != 0) {   // empty partner steps
+        hp.pi.push_back(last);
+        hp.ranges.insert(hp.ranges.end(), 3 * tpw, 0u);
+    }
+    hp.n_pi = static_cast<int>(hp.pi.size());
+    for (int k = 0; k < extra; ++k) hp.pi.push_back(last);                      // targets of the last prefetches
     return hp;
 }
 
@@ -259,9 +347,8 @@ static U *upload(const std::vector<U> &v) {
 }
 
 void free_plan(ApplyPlan &p) {
-    hipFree(p.grp_g);
-    hipFree(p.grp_first);
-    hipFree(p.grp_mid);
+    hipFree(p.pi);
+    hipFree(p.ranges);
     hipFree(p.meta);
     hipFree(p.tile_map);
     hipFree(p.c32);
@@ -274,12 +361,14 @@ void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out) {
     p.bt = bt;
     p.rb = rb;
     p.rot = hp.rot;
+    p.w = hp.w;
     p.n_tiles = hp.n_tiles;
-    p.n_groups = hp.n_groups;
+    p.n_wg = hp.n_wg;
+    p.n_pi = hp.n_pi;
+    for (size_t i = 0; i < hp.hvec.size() && i < 4; ++i) p.hvec[i] = hp.hvec[i];
     try {
-        p.grp_g = upload(hp.grp_g);
-        p.grp_first = upload(hp.grp_first);
-        p.grp_mid = upload(hp.grp_mid);
+        p.pi = upload(hp.pi);
+        p.ranges = upload(hp.ranges);
         p.meta = upload(hp.meta);
         p.tile_map = upload(hp.tile_map);
         std::vector<float> c32(hp.c.begin(), hp.c.end());

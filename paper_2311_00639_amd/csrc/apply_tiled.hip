@@ -79,6 +79,88 @@ __device__ __forceinline__ void apply_terms(typename V2t<T>::type (&acc)[1 << RB
     }
 }
 
+// Register-static terms: a 4-dword record (thread bits of x, thread bits of z, z >> BT,
+// code = (xr << RB) | zr) selects one of (2^RB)^2 compiled paths in which the partner
+// register r ^ xr is a constant LDS offset and the sign of output register r (parity of
+// r & zr) a constant operand sign, so an amplitude costs one LDS read and two FMAs.
+struct TermRec4 {
+    uint32_t xt, zt, zh, code;
+};
+
+template <typename T, int TB, int RB, int XR, int ZR, bool IM>
+__device__ __forceinline__ void term_static(typename V2t<T>::type (&acc)[1 << RB], const typename V2t<T>::type *bs,
+                                            T cl) {
+    using V = typename V2t<T>::type;
+    constexpr int R = 1 << RB;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const V q = bs[(r ^ XR) << TB];
+        const T cr = (__builtin_popcount(r & ZR) & 1) ? -cl : cl;
+        if (IM) {
+            acc[r].x -= cr * q.y;
+            acc[r].y += cr * q.x;
+        } else {
+            acc[r].x += cr * q.x;
+            acc[r].y += cr * q.y;
+        }
+    }
+}
+
+template <typename T, int TB, int RB, bool IM, int C>
+__device__ __forceinline__ void term_case(typename V2t<T>::type (&acc)[1 << RB], const typename V2t<T>::type *bs,
+                                          T cl) {
+    constexpr int R = 1 << RB;
+    if constexpr (C < R * R) term_static<T, TB, RB, C / R, C % R, IM>(acc, bs, cl);
+}
+
+template <typename T, int BT, int RB, bool IM>
+__device__ __forceinline__ void apply_terms_static(typename V2t<T>::type (&acc)[1 << RB],
+                                                   const typename V2t<T>::type *b,
+                                                   const TermRec4 *__restrict__ recs, const T *__restrict__ coef,
+                                                   int t0, int t1, uint32_t tile, uint32_t tid) {
+    using V = typename V2t<T>::type;
+    constexpr int TB = BT - RB;
+    if (t0 >= t1) return;
+    TermRec4 nxt = recs[t0];
+    T cn = coef[t0];
+    for (int t = t0; t < t1; ++t) {
+        const TermRec4 rec = nxt;                       // wave-uniform: scalar loads
+        const T c = cn;
+        nxt = recs[t + 1];
+        cn = coef[t + 1];
+        const uint32_t par = (__popc(tile & rec.zh) + __popc(tid & rec.zt)) & 1u;
+        const T cl = flip_sign(c, par << 31);
+        const V *bs = b + (tid ^ rec.xt);
+#define SYK_C4(B)                                                  \
+    case B + 0: term_case<T, TB, RB, IM, B + 0>(acc, bs, cl); break; \
+    case B + 1: term_case<T, TB, RB, IM, B + 1>(acc, bs, cl); break; \
+    case B + 2: term_case<T, TB, RB, IM, B + 2>(acc, bs, cl); break; \
+    case B + 3: term_case<T, TB, RB, IM, B + 3>(acc, bs, cl); break;
+        switch (rec.code) {
+            SYK_C4(0) SYK_C4(4) SYK_C4(8) SYK_C4(12) SYK_C4(16) SYK_C4(20) SYK_C4(24) SYK_C4(28)
+            SYK_C4(32) SYK_C4(36) SYK_C4(40) SYK_C4(44) SYK_C4(48) SYK_C4(52) SYK_C4(56) SYK_C4(60)
+            default: break;
+        }
+#undef SYK_C4
+    }
+}
+
+// one group's terms (real-phase terms [t0, tm), i-phase terms [tm, t1)) in either record form
+template <typename T, int BT, int RB, int SR>
+__device__ __forceinline__ void group_terms(typename V2t<T>::type (&acc)[1 << RB], const typename V2t<T>::type *b,
+                                            const void *recs, const T *__restrict__ coef, int t0, int tm, int t1,
+                                            uint32_t tile, uint32_t tid) {
+    if constexpr (SR) {
+        const TermRec4 *r = static_cast<const TermRec4 *>(recs);
+        apply_terms_static<T, BT, RB, false>(acc, b, r, coef, t0, tm, tile, tid);
+        apply_terms_static<T, BT, RB, true>(acc, b, r, coef, tm, t1, tile, tid);
+    } else {
+        const TermRec<1 << RB> *r = static_cast<const TermRec<1 << RB> *>(recs);
+        apply_terms<T, BT, RB, false>(acc, b, r, coef, t0, tm, tile, tid);
+        apply_terms<T, BT, RB, true>(acc, b, r, coef, tm, t1, tile, tid);
+    }
+}
+
 // s_waitcnt immediate (GFX9 encoding) that waits until at most `vm` vector-memory
 // operations of this wave are outstanding; expcnt and lgkmcnt are left unconstrained
 constexpr int waitcnt_vm(int vm) { return (vm & 15) | (7 << 4) | (15 << 8) | (((vm >> 4) & 3) << 14); }
@@ -110,55 +192,78 @@ __device__ __forceinline__ V *pick(V *b0, V *b1, V *b2, V *b3) {
     return b3;
 }
 
+// The output tiles of a workgroup: t0 ^ h[i], i < 2^W.
+struct TileSet {
+    uint32_t h[4];
+};
+
 // Partner tiles stream into NBUF LDS buffers by direct loads, NBUF - 1 of them in flight
 // while the current one is consumed; the buffers are distinct LDS objects so that reads
 // of one need not wait for copies into the others.  With NBUF = 1 the copy and the
-// compute of a group alternate inside the workgroup and OCC workgroups share a CU, so one
-// computes while another waits for its tile.  n_groups is a multiple of NBUF (the host
-// pads with empty groups) and grp_g holds NBUF - 1 extra entries.  blockIdx maps to an
-// output tile through tile_map.  The second launch bound (waves per SIMD) keeps OCC
-// workgroups resident.
-template <typename T, int BT, int RB, int NBUF, int OCC>
+// compute of a partner alternate inside the workgroup and OCC workgroups share a CU, so
+// one computes while another waits for its tile.  A workgroup holds 2^W output tiles in
+// registers; partner step k brings tile t0 ^ pi[k] and applies to output tile i the terms
+// [ranges[3(k 2^W + i)], ...] of group pi[k] ^ h[i].  n_pi is a multiple of NBUF (the host
+// pads with empty steps) and pi holds NBUF - 1 extra entries.  The second launch bound
+// (waves per SIMD) keeps OCC workgroups resident.
+template <typename T, int BT, int RB, int NBUF, int OCC, int SR, int W>
 __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) apply_h_tiled(
     const typename V2t<T>::type *__restrict__ x, typename V2t<T>::type *__restrict__ y, uint64_t ld,
-    const uint32_t *__restrict__ tile_map, const uint32_t *__restrict__ grp_g,
-    const uint32_t *__restrict__ grp_first, const uint32_t *__restrict__ grp_mid, int n_groups,
-    const TermRec<1 << RB> *__restrict__ recs, const T *__restrict__ coef, LanczosFuse<T> lf) {
+    const uint32_t *__restrict__ tile_map, TileSet hs, const uint32_t *__restrict__ pi,
+    const uint32_t *__restrict__ ranges, int n_pi, const void *__restrict__ recs, const T *__restrict__ coef,
+    LanczosFuse<T> lf) {
     using V = typename V2t<T>::type;
     constexpr int NT = 1 << (BT - RB);
     constexpr int R = 1 << RB;
+    constexpr int TPW = 1 << W;
     constexpr int TILE = 1 << BT;
     constexpr int PER = TILE * 2 * static_cast<int>(sizeof(T)) / (NT * 16);
     static_assert(NBUF >= 1 && NBUF <= 4, "1 to 4 LDS buffers");
+    static_assert(W >= 0 && W <= 2, "1, 2 or 4 tiles per workgroup");
     __shared__ V b0[TILE];
     __shared__ V b1[NBUF > 1 ? TILE : 1];
     __shared__ V b2[NBUF > 2 ? TILE : 1];
     __shared__ V b3[NBUF > 3 ? TILE : 1];
 
     const uint32_t tid = threadIdx.x;
-    const uint32_t tile = tile_map[blockIdx.x];
+    const uint32_t t0 = tile_map[blockIdx.x];
     const uint64_t vo = static_cast<uint64_t>(blockIdx.y) * ld;
     const V *xv = x + vo;
     V *yv = y + vo;
-    auto partner = [&](int gi) { return xv + (static_cast<uint64_t>(tile ^ grp_g[gi]) << BT); };
+    auto partner = [&](int k) __attribute__((always_inline)) { return xv + (static_cast<uint64_t>(t0 ^ pi[k]) << BT); };
 
-    V acc[R];
+    V acc[TPW][R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = V{T(0), T(0)};
+    for (int i = 0; i < TPW; ++i)
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[i][r] = V{T(0), T(0)};   // fully unrolled: constant indices
+
+    // the tile index must be a compile-time constant: acc[i] stays in registers
+    auto terms_of = [&](const V *b, int k) __attribute__((always_inline)) {
+        const uint32_t *rg = ranges + static_cast<size_t>(k) * TPW * 3;
+        auto one = [&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            group_terms<T, BT, RB, SR>(acc[i], b, recs, coef, static_cast<int>(rg[3 * i]),
+                                       static_cast<int>(rg[3 * i + 1]), static_cast<int>(rg[3 * i + 2]),
+                                       t0 ^ hs.h[i], tid);
+        };
+        one(std::integral_constant<int, 0>{});
+        if constexpr (TPW > 1) one(std::integral_constant<int, 1>{});
+        if constexpr (TPW > 2) {
+            one(std::integral_constant<int, 2>{});
+            one(std::integral_constant<int, 3>{});
+        }
+    };
 
     if constexpr (NBUF == 1) {
-        for (int gi = 0; gi < n_groups; ++gi) {
-            // the previous group's reads of b0 ended at the barrier closing its step
-            dma_tile<T, BT, RB>(partner(gi), b0, tid);
+        for (int k = 0; k < n_pi; ++k) {
+            // the previous step's reads of b0 ended at the barrier closing it
+            dma_tile<T, BT, RB>(partner(k), b0, tid);
             __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
             asm volatile("" ::: "memory");
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
-            const int t0 = static_cast<int>(grp_first[gi]);
-            const int tm = static_cast<int>(grp_mid[gi]);
-            const int t1 = static_cast<int>(grp_first[gi + 1]);
-            apply_terms<T, BT, RB, false>(acc, b0, recs, coef, t0, tm, tile, tid);
-            apply_terms<T, BT, RB, true>(acc, b0, recs, coef, tm, t1, tile, tid);
+            terms_of(b0, k);
             asm volatile("" ::: "memory");
             __builtin_amdgcn_s_barrier();
             asm volatile("" ::: "memory");
@@ -167,11 +272,11 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
         dma_tile<T, BT, RB>(partner(0), b0, tid);
         if constexpr (NBUF > 2) dma_tile<T, BT, RB>(partner(1), b1, tid);
         if constexpr (NBUF > 3) dma_tile<T, BT, RB>(partner(2), b2, tid);
-        for (int g0 = 0; g0 < n_groups; g0 += NBUF) {
-            auto step = [&](auto kc) {
+        for (int k0 = 0; k0 < n_pi; k0 += NBUF) {
+            auto step = [&](auto kc) __attribute__((always_inline)) {
                 constexpr int K = decltype(kc)::value;
-                const int gi = g0 + K;
-                // this group's copy was issued NBUF - 1 steps ago; NBUF - 2 copies are newer.
+                const int k = k0 + K;
+                // this step's copy was issued NBUF - 1 steps ago; NBUF - 2 copies are newer.
                 // A bare s_barrier (no fence): each wave has waited for its own pieces of the
                 // tile, LDS is coherent within the CU, and the barrier also guarantees that
                 // every wave is done reading the buffer the next copy overwrites.
@@ -179,13 +284,8 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
                 asm volatile("" ::: "memory");   // no LDS access or copy moves across the barrier
                 __builtin_amdgcn_s_barrier();
                 asm volatile("" ::: "memory");
-                dma_tile<T, BT, RB>(partner(gi + NBUF - 1), pick<(K + NBUF - 1) % NBUF>(b0, b1, b2, b3), tid);
-                const V *b = pick<K>(b0, b1, b2, b3);
-                const int t0 = static_cast<int>(grp_first[gi]);
-                const int tm = static_cast<int>(grp_mid[gi]);
-                const int t1 = static_cast<int>(grp_first[gi + 1]);
-                apply_terms<T, BT, RB, false>(acc, b, recs, coef, t0, tm, tile, tid);
-                apply_terms<T, BT, RB, true>(acc, b, recs, coef, tm, t1, tile, tid);
+                dma_tile<T, BT, RB>(partner(k + NBUF - 1), pick<(K + NBUF - 1) % NBUF>(b0, b1, b2, b3), tid);
+                terms_of(pick<K>(b0, b1, b2, b3), k);
             };
             step(std::integral_constant<int, 0>{});
             step(std::integral_constant<int, 1>{});
@@ -194,41 +294,63 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
         }
     }
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));      // no copy may still target LDS at exit
-    V *dst = yv + (static_cast<uint64_t>(tile) << BT);
     if (lf.partials == nullptr) {
         // outputs are not re-read by this kernel: stream them past the caches
+        auto store = [&](auto ic) __attribute__((always_inline)) {
+            constexpr int i = decltype(ic)::value;
+            V *dst = yv + (static_cast<uint64_t>(t0 ^ hs.h[i]) << BT);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            __builtin_nontemporal_store(acc[r].x, &dst[r * NT + tid].x);
-            __builtin_nontemporal_store(acc[r].y, &dst[r * NT + tid].y);
+            for (int r = 0; r < R; ++r) {
+                __builtin_nontemporal_store(acc[i][r].x, &dst[r * NT + tid].x);
+                __builtin_nontemporal_store(acc[i][r].y, &dst[r * NT + tid].y);
+            }
+        };
+        store(std::integral_constant<int, 0>{});
+        if constexpr (TPW > 1) store(std::integral_constant<int, 1>{});
+        if constexpr (TPW > 2) {
+            store(std::integral_constant<int, 2>{});
+            store(std::integral_constant<int, 3>{});
         }
         return;
     }
-    // Lanczos epilogue: w = H v_j - beta_{j-1} v_{j-1}, and this tile's shares of
+    // Lanczos epilogue: w = H v_j - beta_{j-1} v_{j-1}, and this workgroup's shares of
     // <v_j, w> (re, im), ||w||^2 and ||v_j||^2 in double
     const T bp = lf.vprev ? static_cast<T>(sqrt(lf.beta2_prev[0])) : T(0);
-    const V *vp = reinterpret_cast<const V *>(lf.vprev) + (static_cast<uint64_t>(tile) << BT);
-    const V *vc = reinterpret_cast<const V *>(lf.vcur) + (static_cast<uint64_t>(tile) << BT);
     double sum[4] = {0.0, 0.0, 0.0, 0.0};
-    auto epilogue = [&](auto has_prev) {
+    auto epi_tile = [&](auto has_prev, auto ic) __attribute__((always_inline)) {
+        constexpr int i = decltype(ic)::value;
+        {
+            const uint64_t base = static_cast<uint64_t>(t0 ^ hs.h[i]) << BT;
+            V *dst = yv + base;
+            const V *vp = reinterpret_cast<const V *>(lf.vprev) + base;
+            const V *vc = reinterpret_cast<const V *>(lf.vcur) + base;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = r * NT + tid;
-            V w = acc[r];
-            if constexpr (decltype(has_prev)::value) {
-                const V p = vp[i];
-                w.x -= bp * p.x;
-                w.y -= bp * p.y;
+            for (int r = 0; r < R; ++r) {
+                const int m = r * NT + tid;
+                V w = acc[i][r];
+                if constexpr (decltype(has_prev)::value) {
+                    const V p = vp[m];
+                    w.x -= bp * p.x;
+                    w.y -= bp * p.y;
+                }
+                const V c = vc[m];
+                dst[m] = w;
+                sum[0] += static_cast<double>(c.x) * w.x + static_cast<double>(c.y) * w.y;
+                sum[1] += static_cast<double>(c.x) * w.y - static_cast<double>(c.y) * w.x;
+                sum[2] += static_cast<double>(w.x) * w.x + static_cast<double>(w.y) * w.y;
+                sum[3] += static_cast<double>(c.x) * c.x + static_cast<double>(c.y) * c.y;
+                // bound the loads in flight: with several workgroups per CU the register
+                // budget is 64 VGPRs
+                if (r % 2 == 1) __builtin_amdgcn_sched_barrier(0);
             }
-            const V c = vc[i];
-            dst[i] = w;
-            sum[0] += static_cast<double>(c.x) * w.x + static_cast<double>(c.y) * w.y;
-            sum[1] += static_cast<double>(c.x) * w.y - static_cast<double>(c.y) * w.x;
-            sum[2] += static_cast<double>(w.x) * w.x + static_cast<double>(w.y) * w.y;
-            sum[3] += static_cast<double>(c.x) * c.x + static_cast<double>(c.y) * c.y;
-            // bound the loads in flight: with several workgroups per CU the register
-            // budget is 64 VGPRs
-            if (r % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    auto epilogue = [&](auto has_prev) __attribute__((always_inline)) {
+        epi_tile(has_prev, std::integral_constant<int, 0>{});
+        if constexpr (TPW > 1) epi_tile(has_prev, std::integral_constant<int, 1>{});
+        if constexpr (TPW > 2) {
+            epi_tile(has_prev, std::integral_constant<int, 2>{});
+            epi_tile(has_prev, std::integral_constant<int, 3>{});
         }
     };
     if (lf.vprev)
@@ -252,7 +374,7 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
 
 }  // namespace
 
-template <typename T, int BT, int RB, int NBUF, int OCC>
+template <typename T, int BT, int RB, int NBUF, int OCC, int SR, int W>
 static void launch_variant(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_t ld, const LanczosFuse<T> &lf,
                            hipStream_t s) {
     using V = typename V2t<T>::type;
@@ -261,11 +383,12 @@ static void launch_variant(const ApplyPlan &pl, const T *x, T *y, int nvec, uint
         coef = pl.c32;
     else
         coef = pl.c64;
-    dim3 grid(pl.n_tiles, nvec);
-    hipLaunchKernelGGL((apply_h_tiled<T, BT, RB, NBUF, OCC>), grid, dim3(1 << (BT - RB)), 0, s,
-                       reinterpret_cast<const V *>(x), reinterpret_cast<V *>(y), ld, pl.tile_map, pl.grp_g,
-                       pl.grp_first, pl.grp_mid, pl.n_groups,
-                       reinterpret_cast<const TermRec<1 << RB> *>(pl.meta), coef, lf);
+    if (pl.w != W) fail(SYK_EDEVICE, "plan and kernel disagree on tiles per workgroup");
+    TileSet hs{{pl.hvec[0], pl.hvec[1], pl.hvec[2], pl.hvec[3]}};
+    dim3 grid(pl.n_wg, nvec);
+    hipLaunchKernelGGL((apply_h_tiled<T, BT, RB, NBUF, OCC, SR, W>), grid, dim3(1 << (BT - RB)), 0, s,
+                       reinterpret_cast<const V *>(x), reinterpret_cast<V *>(y), ld, pl.tile_map, hs, pl.pi,
+                       pl.ranges, pl.n_pi, static_cast<const void *>(pl.meta), coef, lf);
     SYK_HIP(hipGetLastError());
 }
 
@@ -275,25 +398,29 @@ void launch_apply_tiled(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_
     const TiledVariant &v = tiled_variants<T>()[pl.variant];
     const LanczosFuse<T> none{};
     if (lf && nvec != 1) fail(SYK_EDEVICE, "the fused Lanczos epilogue takes one vector");
-#define SYK_TV(BT, RB, NB, OC)                                                      \
-    if (v.bt == BT && v.rb == RB && v.nbuf == NB && v.occ == OC) {                  \
-        launch_variant<T, BT, RB, NB, OC>(pl, x, y, nvec, ld, lf ? *lf : none, s);  \
-        return;                                                                     \
+#define SYK_TV(BT, RB, NB, OC, SR, W)                                                       \
+    if (v.bt == BT && v.rb == RB && v.nbuf == NB && v.occ == OC && v.sr == SR && v.w == W) {    \
+        launch_variant<T, BT, RB, NB, OC, SR, W>(pl, x, y, nvec, ld, lf ? *lf : none, s);       \
+        return;                                                                                 \
     }
     if constexpr (sizeof(T) == 4) {
-        SYK_TV(13, 3, 2, 1)
-        SYK_TV(13, 3, 1, 2)
-        SYK_TV(12, 3, 1, 4)
-        SYK_TV(12, 3, 2, 2)
-        SYK_TV(12, 2, 4, 1)
-        SYK_TV(11, 2, 2, 4)
+        SYK_TV(13, 3, 2, 1, 0, 0)
+        SYK_TV(13, 3, 1, 2, 0, 0)
+        SYK_TV(12, 3, 2, 2, 0, 0)
+        SYK_TV(12, 2, 4, 1, 0, 0)
+        SYK_TV(13, 3, 2, 1, 1, 0)
+        SYK_TV(13, 3, 2, 1, 0, 1)
+        SYK_TV(13, 3, 2, 1, 0, 2)
+        SYK_TV(12, 3, 2, 2, 0, 1)
     } else {
-        SYK_TV(12, 2, 2, 1)
-        SYK_TV(12, 2, 1, 2)
-        SYK_TV(11, 2, 1, 4)
-        SYK_TV(11, 2, 2, 2)
-        SYK_TV(11, 1, 4, 1)
-        SYK_TV(10, 1, 2, 4)
+        SYK_TV(12, 2, 2, 1, 0, 0)
+        SYK_TV(12, 2, 1, 2, 0, 0)
+        SYK_TV(11, 2, 2, 2, 0, 0)
+        SYK_TV(11, 1, 4, 1, 0, 0)
+        SYK_TV(12, 2, 2, 1, 1, 0)
+        SYK_TV(12, 2, 2, 1, 0, 1)
+        SYK_TV(12, 2, 2, 1, 0, 2)
+        SYK_TV(11, 2, 2, 2, 0, 1)
     }
 #undef SYK_TV
     fail(SYK_EDEVICE, "unknown tiled apply_H variant");

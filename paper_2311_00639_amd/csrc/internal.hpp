@@ -51,16 +51,20 @@ struct DeviceTables {            // per device, per block: real terms first, the
 // Compiled variant of the tiled apply_H kernel: tiles of 2^bt amplitudes, 2^rb per
 // thread, nbuf LDS partner buffers (nbuf - 1 copies in flight; 1 = copy, then compute),
 // pf extra partner entries at the end of the group list, occ workgroups resident per CU
-// (the planner's XCD-resident subspace has dimension 5 + log2(occ)).
+// (the planner's XCD-resident subspace has dimension 5 + log2(occ)); sr = 1: each term's
+// register permutation and register signs select a compiled code path (4-dword term
+// records), sr = 0: they are read from the term record (4 + 2 * 2^rb dwords); each
+// workgroup keeps 2^w output tiles in registers and streams the union of their partner
+// tiles once.
 struct TiledVariant {
-    int bt, rb, nbuf, pf, occ;
+    int bt, rb, nbuf, pf, occ, sr, w;   // w: each workgroup holds 2^w output tiles
 };
 inline int resident_bits(const TiledVariant &v) { return 5 + (v.occ >= 4 ? 2 : v.occ >= 2 ? 1 : 0); }
 template <typename T>
 const std::vector<TiledVariant> &tiled_variants();
-// variant used before (or without) autotuning
+// variant used before (or without) autotuning, for blocks of 2^L amplitudes
 template <typename T>
-int default_variant();
+int default_variant(int L);
 // smallest block (in qubits) served by the tiled kernel
 constexpr int kTiledMinL = 18;
 
@@ -69,14 +73,15 @@ uint32_t rotr_bits(uint32_t v, int s, int L);
 uint32_t rotl_bits(uint32_t v, int s, int L);
 
 struct ApplyPlan {
-    int bt = 0, rb = 0, rot = 0, variant = 0;
-    uint32_t n_tiles = 0;
-    uint32_t *tile_map = nullptr;    // n_tiles: blockIdx -> output tile
-    int n_groups = 0;
-    uint32_t *grp_g = nullptr;       // n_groups: partner tile offset g = x >> BT
-    uint32_t *grp_first = nullptr;   // n_groups + 1: first term of each group
-    uint32_t *grp_mid = nullptr;     // n_groups: first i-phase term (real-phase terms come first)
-    uint32_t *meta = nullptr;        // K records of 4 + 2R dwords (see apply_tiled.hip)
+    int bt = 0, rb = 0, rot = 0, variant = 0, w = 0;
+    uint32_t n_tiles = 0;            // output tiles
+    uint32_t n_wg = 0;               // workgroups (n_tiles >> w)
+    uint32_t hvec[4] = {0, 0, 0, 0}; // tiles of a workgroup: t0 ^ hvec[i], i < 2^w
+    uint32_t *tile_map = nullptr;    // n_wg: blockIdx -> t0
+    int n_pi = 0;
+    uint32_t *pi = nullptr;          // n_pi + pf partner offsets (partner tile t0 ^ pi)
+    uint32_t *ranges = nullptr;      // n_pi * 2^w * 3 term ranges (first, mid, end)
+    uint32_t *meta = nullptr;        // K + 1 term records (see apply_tiled.hip)
     float *c32 = nullptr;
     double *c64 = nullptr;
 };

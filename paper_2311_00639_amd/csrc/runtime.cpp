@@ -65,20 +65,35 @@ const DeviceTables &Hamiltonian::tables(int blk) {
 
 template <>
 const std::vector<TiledVariant> &tiled_variants<float>() {
-    static const std::vector<TiledVariant> v = {{13, 3, 2, 1, 1}, {13, 3, 1, 0, 2}, {12, 3, 1, 0, 4},
-                                                {12, 3, 2, 1, 2}, {12, 2, 4, 3, 1}, {11, 2, 2, 1, 4}};
+    static const std::vector<TiledVariant> v = {{13, 3, 2, 1, 1, 0, 0}, {13, 3, 1, 0, 2, 0, 0}, {12, 3, 2, 1, 2, 0, 0},
+                                                {12, 2, 4, 3, 1, 0, 0}, {13, 3, 2, 1, 1, 1, 0}, {13, 3, 2, 1, 1, 0, 1},
+                                                {13, 3, 2, 1, 1, 0, 2}, {12, 3, 2, 1, 2, 0, 1}};
     return v;
 }
 template <>
 const std::vector<TiledVariant> &tiled_variants<double>() {
-    static const std::vector<TiledVariant> v = {{12, 2, 2, 1, 1}, {12, 2, 1, 0, 2}, {11, 2, 1, 0, 4},
-                                                {11, 2, 2, 1, 2}, {11, 1, 4, 3, 1}, {10, 1, 2, 1, 4}};
+    static const std::vector<TiledVariant> v = {{12, 2, 2, 1, 1, 0, 0}, {12, 2, 1, 0, 2, 0, 0}, {11, 2, 2, 1, 2, 0, 0},
+                                                {11, 1, 4, 3, 1, 0, 0}, {12, 2, 2, 1, 1, 1, 0}, {12, 2, 2, 1, 1, 0, 1},
+                                                {12, 2, 2, 1, 1, 0, 2}, {11, 2, 2, 1, 2, 0, 1}};
     return v;
 }
-template <>
-int default_variant<float>() { return 0; }
-template <>
-int default_variant<double>() { return 0; }
+// Before (or without) autotuning: the first of a preference order (four, then two, then
+// one tile per workgroup, double-buffered; the fastest at N = 48-56 when measured) whose
+// grid still has >= 256 workgroups, else the variant with the most workgroups.
+template <typename T>
+int default_variant(int L) {
+    const auto &v = tiled_variants<T>();
+    for (int pref : {6, 5, 0}) {
+        const TiledVariant &tv = v.at(pref);
+        if (L >= tv.bt + tv.w + 8) return pref;
+    }
+    int best = 0;
+    for (int i = 1; i < static_cast<int>(v.size()); ++i)
+        if (v[i].bt + v[i].w < v[best].bt + v[best].w) best = i;
+    return best;
+}
+template int default_variant<float>(int);
+template int default_variant<double>(int);
 
 template <typename T>
 const ApplyPlan &Hamiltonian::plan(int blk, int rot, int variant) {
@@ -88,9 +103,9 @@ const ApplyPlan &Hamiltonian::plan(int blk, int rot, int variant) {
     const TiledVariant &tv = tiled_variants<T>().at(variant);
     std::lock_guard<std::mutex> g(dev_mu);
     ApplyPlan &p = plans[std::make_tuple(blk, prec, d, rot, variant)];
-    if (p.grp_g) return p;
+    if (p.pi) return p;
     HostPlan hp = build_host_plan(block_terms[blk], L, tv.bt, tv.rb, tv.nbuf, tv.pf, rot, 2 * sizeof(T),
-                                  resident_bits(tv));
+                                  resident_bits(tv), tv.sr, tv.w);
     upload_plan(hp, tv.bt, tv.rb, p);
     p.variant = variant;
     return p;
@@ -105,7 +120,7 @@ int Hamiltonian::internal_rotation(int variant) {
     std::lock_guard<std::mutex> g(dev_mu);
     int &r = rotation[prec][variant];
     const TiledVariant &tv = tiled_variants<T>().at(variant);
-    if (r < 0) r = choose_rotation(block_terms[0], L, tv.bt, resident_bits(tv));
+    if (r < 0) r = choose_rotation(block_terms[0], L, tv.bt, resident_bits(tv), tv.w);
     return r;
 }
 template int Hamiltonian::internal_rotation<float>(int);
@@ -117,7 +132,7 @@ int Hamiltonian::variant() {
     if (hipGetDevice(&d) != hipSuccess) d = 0;       // host-only queries: nothing tuned yet
     std::lock_guard<std::mutex> g(dev_mu);
     auto it = tuned.find({sizeof(T) == 8 ? 1 : 0, d});
-    return it == tuned.end() ? default_variant<T>() : it->second;
+    return it == tuned.end() ? default_variant<T>(L) : it->second;
 }
 template int Hamiltonian::variant<float>();
 template int Hamiltonian::variant<double>();
@@ -139,9 +154,9 @@ int apply_block_lanczos(Hamiltonian &h, int blk, int rot, const T *x, T *y, cons
                         hipStream_t s) {
     if (!use_tiled<T>(h.L)) fail(SYK_EDEVICE, "the fused Lanczos step needs a tiled block");
     const ApplyPlan &pl = h.plan<T>(blk, rot, h.variant<T>());
-    if (pl.n_tiles > lanczos_partials_max(h.L)) fail(SYK_EDEVICE, "partials buffer too small");
+    if (pl.n_wg > lanczos_partials_max(h.L)) fail(SYK_EDEVICE, "partials buffer too small");
     launch_apply_tiled<T>(pl, x, y, 1, 1ULL << h.L, s, &lf);
-    return static_cast<int>(pl.n_tiles);
+    return static_cast<int>(pl.n_wg);
 }
 template int apply_block_lanczos<float>(Hamiltonian &, int, int, const float *, float *,
                                         const LanczosFuse<float> &, hipStream_t);
@@ -169,13 +184,13 @@ int autotune(Hamiltonian &h, T *x, T *y, hipStream_t s, bool force, std::vector<
     hipEvent_t e0, e1;
     SYK_HIP(hipEventCreate(&e0));
     SYK_HIP(hipEventCreate(&e1));
-    int best = default_variant<T>();
+    int best = default_variant<T>(h.L);
     float best_ms = 1e30f;
     if (times) times->assign(vars.size(), -1.0f);
     try {
         launch_haar_raw<T>(1, 0, h.L - 1, 0, x, x + n, part, np, s);     // any finite data
         for (int v = 0; v < static_cast<int>(vars.size()); ++v) {
-            if (vars[v].bt + 3 > h.L) continue;                          // needs >= 8 tiles
+            if (vars[v].bt + vars[v].w + 3 > h.L) continue;              // needs >= 8 workgroups
             const ApplyPlan &pl = h.plan<T>(0, h.internal_rotation<T>(v), v);
             launch_apply_tiled<T>(pl, x, y, 1, n, s);                    // warm-up
             SYK_HIP(hipEventRecord(e0, s));
@@ -217,7 +232,7 @@ Hamiltonian::~Hamiltonian() {
             }
     }
     for (auto &kv : plans)
-        if (kv.second.grp_g) {
+        if (kv.second.pi) {
             if (have) hipSetDevice(std::get<2>(kv.first));
             free_plan(kv.second);
         }

@@ -147,3 +147,23 @@ def test_batch_argument_checks_without_gpu():
     with pytest.raises(syk.SykError) as e:
         syk.otoc_batch([(24, 2, 1, 23, 22, 1)], 1.0, [1.0, 0.5])
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("dt", [syk.C64, syk.C128])
+def test_plan_describe_every_variant_N56(dt):
+    """Every compiled tiled variant plans the N = 56 block: the consistency checks inside
+    the call (tiles covered once, every term applied once per tile) pass, and holding
+    several tiles per workgroup streams fewer partner tiles per output tile."""
+    h = syk.create_hamiltonian(56, 4, 4, 56)
+    per_tile = {}
+    for v in range(8):
+        syk.select_variant(h, dt, v)
+        d = syk.plan_describe(h, 0, dt, -1)
+        assert d["variant"] == v and d["tiled"] == 1
+        assert d["n_tiles"] == 1 << (27 - d["tile_bits"])
+        assert d["n_groups"] <= d["n_partners"] <= d["n_groups"] * d["tiles_per_wg"]
+        per_tile.setdefault(d["tile_bits"], {})[d["tiles_per_wg"]] = d["n_partners"] / d["tiles_per_wg"]
+    for bt, m in per_tile.items():
+        for tpw, p in m.items():
+            if tpw > 1:
+                assert p < m.get(1, 1e9)
