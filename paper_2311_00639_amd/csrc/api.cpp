@@ -499,6 +499,6 @@ const char *syk_status_string(syk_status s) {
 
 const char *syk_last_error(void) { return g_last_error.c_str(); }
 
-const char *syk_kernel_revision(void) { return "tiled-multi-8"; }
+const char *syk_kernel_revision(void) { return "tiled-multi-9"; }
 
 }  // extern "C"

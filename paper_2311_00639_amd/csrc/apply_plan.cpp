@@ -365,7 +365,7 @@ void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out) {
     p.n_tiles = hp.n_tiles;
     p.n_wg = hp.n_wg;
     p.n_pi = hp.n_pi;
-    for (size_t i = 0; i < hp.hvec.size() && i < 4; ++i) p.hvec[i] = hp.hvec[i];
+    for (size_t i = 0; i < hp.hvec.size() && i < 8; ++i) p.hvec[i] = hp.hvec[i];
     try {
         p.pi = upload(hp.pi);
         p.ranges = upload(hp.ranges);

@@ -194,8 +194,17 @@ __device__ __forceinline__ V *pick(V *b0, V *b1, V *b2, V *b3) {
 
 // The output tiles of a workgroup: t0 ^ h[i], i < 2^W.
 struct TileSet {
-    uint32_t h[4];
+    uint32_t h[8];
 };
+
+// f(integral_constant<int, i>) for i = 0 .. n - 1, each with a compile-time index
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
 
 // Partner tiles stream into NBUF LDS buffers by direct loads, NBUF - 1 of them in flight
 // while the current one is consumed; the buffers are distinct LDS objects so that reads
@@ -219,7 +228,7 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
     constexpr int TILE = 1 << BT;
     constexpr int PER = TILE * 2 * static_cast<int>(sizeof(T)) / (NT * 16);
     static_assert(NBUF >= 1 && NBUF <= 4, "1 to 4 LDS buffers");
-    static_assert(W >= 0 && W <= 2, "1, 2 or 4 tiles per workgroup");
+    static_assert(W >= 0 && W <= 3, "1 to 8 tiles per workgroup");
     __shared__ V b0[TILE];
     __shared__ V b1[NBUF > 1 ? TILE : 1];
     __shared__ V b2[NBUF > 2 ? TILE : 1];
@@ -247,12 +256,7 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
                                        static_cast<int>(rg[3 * i + 1]), static_cast<int>(rg[3 * i + 2]),
                                        t0 ^ hs.h[i], tid);
         };
-        one(std::integral_constant<int, 0>{});
-        if constexpr (TPW > 1) one(std::integral_constant<int, 1>{});
-        if constexpr (TPW > 2) {
-            one(std::integral_constant<int, 2>{});
-            one(std::integral_constant<int, 3>{});
-        }
+        static_for<0, TPW>(one);
     };
 
     if constexpr (NBUF == 1) {
@@ -305,17 +309,17 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
                 __builtin_nontemporal_store(acc[i][r].y, &dst[r * NT + tid].y);
             }
         };
-        store(std::integral_constant<int, 0>{});
-        if constexpr (TPW > 1) store(std::integral_constant<int, 1>{});
-        if constexpr (TPW > 2) {
-            store(std::integral_constant<int, 2>{});
-            store(std::integral_constant<int, 3>{});
-        }
+        static_for<0, TPW>(store);
         return;
     }
     // Lanczos epilogue: w = H v_j - beta_{j-1} v_{j-1}, and this workgroup's shares of
     // <v_j, w> (re, im), ||w||^2 and ||v_j||^2 in double
-    const T bp = lf.vprev ? static_cast<T>(sqrt(lf.beta2_prev[0])) : T(0);
+    // scales of the unnormalised basis (see LanczosFuse)
+    // (a zero vector after an exact breakdown stays zero)
+    const double nj = lf.j >= 1 ? sqrt(lf.beta2[lf.j]) : 1.0;
+    const double njm = lf.j >= 2 ? sqrt(lf.beta2[lf.j - 1]) : 1.0;
+    const T sc = nj > 1e-300 ? static_cast<T>(1.0 / nj) : T(0);
+    const T bp = (lf.vprev && njm > 1e-300) ? static_cast<T>(nj / njm) : T(0);
     double sum[4] = {0.0, 0.0, 0.0, 0.0};
     auto epi_tile = [&](auto has_prev, auto ic) __attribute__((always_inline)) {
         constexpr int i = decltype(ic)::value;
@@ -327,13 +331,13 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int m = r * NT + tid;
-                V w = acc[i][r];
+                V w = V{sc * acc[i][r].x, sc * acc[i][r].y};
                 if constexpr (decltype(has_prev)::value) {
                     const V p = vp[m];
                     w.x -= bp * p.x;
                     w.y -= bp * p.y;
                 }
-                const V c = vc[m];
+                const V c = V{sc * vc[m].x, sc * vc[m].y};
                 dst[m] = w;
                 sum[0] += static_cast<double>(c.x) * w.x + static_cast<double>(c.y) * w.y;
                 sum[1] += static_cast<double>(c.x) * w.y - static_cast<double>(c.y) * w.x;
@@ -346,12 +350,7 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
         }
     };
     auto epilogue = [&](auto has_prev) __attribute__((always_inline)) {
-        epi_tile(has_prev, std::integral_constant<int, 0>{});
-        if constexpr (TPW > 1) epi_tile(has_prev, std::integral_constant<int, 1>{});
-        if constexpr (TPW > 2) {
-            epi_tile(has_prev, std::integral_constant<int, 2>{});
-            epi_tile(has_prev, std::integral_constant<int, 3>{});
-        }
+        static_for<0, TPW>([&](auto ic) __attribute__((always_inline)) { epi_tile(has_prev, ic); });
     };
     if (lf.vprev)
         epilogue(std::true_type{});
@@ -384,7 +383,8 @@ static void launch_variant(const ApplyPlan &pl, const T *x, T *y, int nvec, uint
     else
         coef = pl.c64;
     if (pl.w != W) fail(SYK_EDEVICE, "plan and kernel disagree on tiles per workgroup");
-    TileSet hs{{pl.hvec[0], pl.hvec[1], pl.hvec[2], pl.hvec[3]}};
+    TileSet hs{};
+    for (int i = 0; i < 8; ++i) hs.h[i] = pl.hvec[i];
     dim3 grid(pl.n_wg, nvec);
     hipLaunchKernelGGL((apply_h_tiled<T, BT, RB, NBUF, OCC, SR, W>), grid, dim3(1 << (BT - RB)), 0, s,
                        reinterpret_cast<const V *>(x), reinterpret_cast<V *>(y), ld, pl.tile_map, hs, pl.pi,

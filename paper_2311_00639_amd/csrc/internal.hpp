@@ -76,7 +76,7 @@ struct ApplyPlan {
     int bt = 0, rb = 0, rot = 0, variant = 0, w = 0;
     uint32_t n_tiles = 0;            // output tiles
     uint32_t n_wg = 0;               // workgroups (n_tiles >> w)
-    uint32_t hvec[4] = {0, 0, 0, 0}; // tiles of a workgroup: t0 ^ hvec[i], i < 2^w
+    uint32_t hvec[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // tiles of a workgroup: t0 ^ hvec[i], i < 2^w
     uint32_t *tile_map = nullptr;    // n_wg: blockIdx -> t0
     int n_pi = 0;
     uint32_t *pi = nullptr;          // n_pi + pf partner offsets (partner tile t0 ^ pi)
@@ -86,14 +86,19 @@ struct ApplyPlan {
     double *c64 = nullptr;
 };
 
-// Optional epilogue of the tiled apply_H for one Lanczos step: y = H v_j - beta_{j-1} v_{j-1}
-// (vprev may be null, beta2_prev points at beta_{j-1}^2 on the device), and per-workgroup
-// partial sums (re <v_j,y>, im <v_j,y>, ||y||^2, ||v_j||^2) at partials[4 * blockIdx.x].
+// Optional epilogue of the tiled apply_H for Lanczos step j of the fused path, where the
+// basis is stored unnormalised: slot i >= 1 holds u_i with ||u_i|| = sqrt(beta2[i]) (so
+// v_i = u_i / sqrt(beta2[i])), slot 0 holds v_0.  With x = u_j (vcur) the epilogue forms
+//   y = H v_j - beta_{j-1} v_{j-1} = s_j H u_j - (beta_{j-1} s_{j-1}) u_{j-1}
+// (s_i = 1 / ||u_i||, s_0 = 1, beta_{j-1} = ||u_j||; vprev = u_{j-1}, null for j = 0) and
+// per-workgroup partial sums (re <v_j,y>, im <v_j,y>, ||y||^2, ||v_j||^2) at
+// partials[4 * blockIdx.x].
 template <typename T>
 struct LanczosFuse {
     const T *vprev = nullptr;
     const T *vcur = nullptr;
-    const double *beta2_prev = nullptr;
+    const double *beta2 = nullptr;     // device, indexed by basis slot
+    int j = 0;
     double *partials = nullptr;
 };
 
@@ -208,6 +213,11 @@ void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_ou
 // w <- (w - alpha_re v) / beta, beta = sqrt(beta2[0]); zero if beta underflows
 template <typename T>
 void launch_lanczos_update(T *w, const T *v, const double *alpha, const double *beta2, uint64_t n, hipStream_t s);
+// fused path: w <- w - alpha_j s_j u_j (v = u_j, s_j from beta2[j], j >= 1; 1 for j = 0) and
+// per-block partials of ||w||^2 (reduction_blocks(n) of them)
+template <typename T>
+void launch_lanczos_residual(T *w, const T *v, const double *alpha, const double *beta2, int j, uint64_t n,
+                             double *partials, hipStream_t s);
 template <typename T>
 void launch_scale_copy(const T *src, T *dst, uint64_t n, double scale, hipStream_t s);
 template <typename T>

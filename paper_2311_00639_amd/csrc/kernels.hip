@@ -346,11 +346,11 @@ __global__ void __launch_bounds__(kBlock) lanczos_scalars_kernel(const double *_
     block_sum<4>(acc, tot);
     __syncthreads();
     if (threadIdx.x == 0) {
-        const double a = tot[0];
-        alpha_out[0] = a;
+        alpha_out[0] = tot[0];
         alpha_out[1] = tot[1];
-        const double b2 = tot[2] - 2.0 * a * tot[0] + a * a * tot[3];
-        beta2_out[0] = b2 > 0.0 ? b2 : 0.0;
+        // beta is not formed from these sums (||y||^2 - alpha^2 cancels when the Krylov
+        // space is nearly invariant); the residual pass computes it from the vector
+        if (beta2_out) beta2_out[0] = 0.0;
     }
 }
 
@@ -381,6 +381,37 @@ template <typename T>
 void launch_lanczos_update(T *w, const T *v, const double *alpha, const double *beta2, uint64_t n, hipStream_t s) {
     hipLaunchKernelGGL(lanczos_update<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
                        reinterpret_cast<const V2<T> *>(v), alpha, beta2, n);
+    SYK_HIP(hipGetLastError());
+}
+
+// fused Lanczos: w <- w - (alpha_j / ||u_j||) u_j, with partials of ||w||^2
+template <typename T>
+__global__ void __launch_bounds__(kBlock) lanczos_residual(V2<T> *__restrict__ w, const V2<T> *__restrict__ v,
+                                                           const double *__restrict__ alpha,
+                                                           const double *__restrict__ beta2, int j, uint64_t n,
+                                                           double *__restrict__ partials) {
+    const double nj = j >= 1 ? sqrt(beta2[j]) : 1.0;
+    const double sj = nj > 1e-300 ? 1.0 / nj : 0.0;
+    const T a = static_cast<T>(alpha[0] * sj);
+    double acc[1] = {0.0};
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
+        V2<T> u = w[i];
+        const V2<T> c = v[i];
+        u.x -= a * c.x;
+        u.y -= a * c.y;
+        w[i] = u;
+        acc[0] += static_cast<double>(u.x) * u.x + static_cast<double>(u.y) * u.y;
+    }
+    block_sum<1>(acc, partials + blockIdx.x);
+}
+
+template <typename T>
+void launch_lanczos_residual(T *w, const T *v, const double *alpha, const double *beta2, int j, uint64_t n,
+                             double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(lanczos_residual<T>, dim3(reduction_blocks(n)), dim3(kBlock), 0, s,
+                       reinterpret_cast<V2<T> *>(w), reinterpret_cast<const V2<T> *>(v), alpha, beta2, j, n,
+                       partials);
     SYK_HIP(hipGetLastError());
 }
 
@@ -496,6 +527,8 @@ void launch_subtract_proj(T *w, const T *basis, uint64_t stride, int nb, const d
     template void launch_lanczos_orth2<T>(T *, const T *, const double *, uint64_t, double *, int, hipStream_t);   \
     template void launch_lanczos_normalize<T>(T *, const double *, uint64_t, hipStream_t);                         \
     template void launch_lanczos_update<T>(T *, const T *, const double *, const double *, uint64_t, hipStream_t); \
+    template void launch_lanczos_residual<T>(T *, const T *, const double *, const double *, int, uint64_t,          \
+                                             double *, hipStream_t);                                            \
     template void launch_scale_copy<T>(const T *, T *, uint64_t, double, hipStream_t);                             \
     template void launch_combine<T>(const T *, uint64_t, int, const double *, T *, uint64_t, hipStream_t);         \
     template void launch_subtract_proj<T>(T *, const T *, uint64_t, int, const double *, uint64_t, hipStream_t);   \

@@ -197,16 +197,21 @@ void KrylovRun<T>::iterate(int j, int reorth) {
     if (reorth == 0 && use_tiled<T>(h_.L)) {
         // fused step: the apply epilogue forms w = H v_j - beta v_{j-1} and the sums for
         // alpha_j and beta_j; one more pass normalises
+        // basis slots hold u_i unnormalised (||u_i|| = beta_{i-1}); the scales enter the
+        // apply epilogue, the residual pass and the recombination coefficients
         LanczosFuse<T> lf;
         lf.vprev = j > 0 ? vec(j - 1) : nullptr;
         lf.vcur = vj;
-        lf.beta2_prev = beta2_ + j;
+        lf.beta2 = beta2_;
+        lf.j = j;
         lf.partials = fused_;
         if (timer_) timer_->begin(s_);
         const int np = apply_block_lanczos<T>(h_, blk_, rot_, vj, w, lf, s_);
         if (timer_) timer_->end(s_);
-        launch_lanczos_scalars(fused_, np, alpha_ + 2 * j, beta2_ + j + 1, s_);
-        launch_lanczos_update<T>(w, vj, alpha_ + 2 * j, beta2_ + j + 1, n_, s_);
+        launch_lanczos_scalars(fused_, np, alpha_ + 2 * j, nullptr, s_);
+        launch_lanczos_residual<T>(w, vj, alpha_ + 2 * j, beta2_, j, n_, partials_, s_);
+        launch_reduce_partials(partials_, n_part_, 1, beta2_ + j + 1, s_);
+        unnormalised_ = true;
         return;
     }
     if (timer_) timer_->begin(s_);
@@ -245,6 +250,7 @@ void KrylovRun<T>::run(std::complex<double> z, const T *v, T *out, const syk_kry
             fail(SYK_ENOTCONV, "Krylov propagation exceeded max_substeps");
         launch_scale_copy<T>(cur, vec(0), n_, 1.0 / nrm, s_);
         SYK_HIP(hipMemsetAsync(beta2_, 0, sizeof(double), s_));
+        unnormalised_ = false;
         int k = 0;                 // Lanczos vectors built
         double tau = 0.0;
         bool done = false;
@@ -300,8 +306,11 @@ void KrylovRun<T>::run(std::complex<double> z, const T *v, T *out, const syk_kry
                 te.apply(tau * z, c.data());
                 st.err_est += err(tau);
                 for (int i = 0; i < k; ++i) {
-                    coef[2 * i] = nrm * c[i].real();
-                    coef[2 * i + 1] = nrm * c[i].imag();
+                    // fused path: slot i >= 1 holds u_i = ||u_i|| v_i
+                    const double ni = std::sqrt(hb[i]);
+                    const double sc = (unnormalised_ && i >= 1) ? (ni > 1e-300 ? nrm / ni : 0.0) : nrm;
+                    coef[2 * i] = sc * c[i].real();
+                    coef[2 * i + 1] = sc * c[i].imag();
                 }
             }
         }

@@ -72,6 +72,7 @@ class KrylovRun {
     T *basis_ = nullptr;
     double *partials_ = nullptr, *alpha_ = nullptr, *beta2_ = nullptr, *coef_ = nullptr, *scratch_ = nullptr;
     double *fused_ = nullptr;
+    bool unnormalised_ = false;   // fused path: basis slots >= 1 hold u_i = beta_{i-1} v_i
     int n_part_ = 0;
     ApplyTimer *timer_ = nullptr;
 };
