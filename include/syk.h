@@ -53,6 +53,10 @@ typedef enum {
 } syk_status;
 
 typedef enum { SYK_C64 = 0, SYK_C128 = 1 } syk_dtype;
+typedef enum {
+    SYK_ENSEMBLE_EXACT_K = 0,   /* exactly K = round(k N) distinct 4-subsets, uniform */
+    SYK_ENSEMBLE_BERNOULLI = 1  /* every 4-subset kept with probability p = k N / C(N,4) */
+} syk_ensemble;
 typedef enum { SYK_BLOCK_U = 0, SYK_BLOCK_D = 1 } syk_block;
 
 typedef struct {
@@ -77,6 +81,17 @@ typedef struct {
  * Errors: EINVAL (N odd or outside [6,64], K < 1 or K > C(N,4), out == NULL),
  * EUNSUPPORTED (q != 4), ENOMEM. */
 syk_status syk_create_hamiltonian(int N, int q, double k, uint64_t seed, syk_ham **out);
+
+/* As syk_create_hamiltonian for ensemble SYK_ENSEMBLE_EXACT_K.  SYK_ENSEMBLE_BERNOULLI is the
+ * paper's own ensemble of Eq. (1): p_ijkl ~ B(p) with p = k N / C(N,4) (0 < p <= 1; p = 1
+ * gives the dense SYK model, k = C(N,4) / N), J ~ N(0, 3!/(p N^3)).  Draws from one
+ * SplitMix64 stream seeded with `seed`: one uniform (r>>11) 2^-53 per 4-subset in
+ * lexicographic order, the subset kept iff it is below p; then per kept subset, in order,
+ * J = sigma sqrt(-2 ln u1) cos(2 pi u2) as above.  The number of kept terms K is random
+ * (reported by syk_ham_get_info).  Errors: EINVAL (as above, p outside (0, 1], no term
+ * kept, unknown ensemble), EUNSUPPORTED (q != 4), ENOMEM. */
+syk_status syk_create_hamiltonian_ensemble(int N, int q, double k, uint64_t seed, syk_ensemble ensemble,
+                                           syk_ham **out);
 
 /* Free a handle and its device tables on every device.  NULL is a no-op. */
 syk_status syk_destroy_hamiltonian(syk_ham *h);
@@ -334,6 +349,35 @@ syk_status syk_engine_get_stats(syk_engine *e, syk_engine_stats *st);
 
 /* Cancel everything, join the workers, free all device memory; NULL is a no-op. */
 syk_status syk_engine_destroy(syk_engine *e);
+
+/* ---------------------------------------------------------------- spin operators */
+/* General spin operators on L qubits as sums of Pauli strings c X^x Z^z (Z applied
+ * first, qubit q = bit q; the <bits, coeff> operator lists of supplement Sec. I.A), with
+ * the product, linear combination and adjoint computed exactly by the XOR-and-sign rule
+ * (X^a Z^b)(X^c Z^d) = (-1)^{popcount(b & c)} X^{a^c} Z^{b^d}.  An operator converts to a
+ * handle that syk_apply_H (either block argument) and, when Hermitian, syk_krylov_expm run
+ * through the same kernels: other sparse models on the same path.  Terms are kept sorted
+ * by (x, z) with equal strings merged (exact zeros dropped).  Host-only. */
+typedef struct syk_op syk_op;
+
+/* n terms (x[a], z[a], c_re[a] + i c_im[a]); c_re or c_im may be NULL (zero).  Errors:
+ * EINVAL (L outside [1, 31], a string beyond qubit L-1, non-finite coefficient). */
+syk_status syk_op_create(int L, size_t n, const uint64_t *x, const uint64_t *z, const double *c_re,
+                         const double *c_im, syk_op **out);
+syk_status syk_op_destroy(syk_op *o);                                       /* NULL is a no-op */
+syk_status syk_op_product(const syk_op *a, const syk_op *b, syk_op **out);   /* a b */
+/* alpha a + beta b */
+syk_status syk_op_sum(const syk_op *a, const syk_op *b, double alpha_re, double alpha_im, double beta_re,
+                      double beta_im, syk_op **out);
+syk_status syk_op_adjoint(const syk_op *a, syk_op **out);                    /* a^dagger */
+/* *n = number of terms; arrays (host, cap entries, any may be NULL) receive them. */
+syk_status syk_op_get_terms(const syk_op *a, size_t cap, size_t *n, uint64_t *x, uint64_t *z, double *c_re,
+                            double *c_im);
+syk_status syk_op_is_hermitian(const syk_op *a, int *out);
+/* A handle for syk_apply_H (N reported as 2 (L + 1), block dimension 2^L; both blocks hold
+ * the operator) and, for Hermitian operators, syk_krylov_expm; syk_otoc and syk_green
+ * refuse it (EUNSUPPORTED).  Errors: EINVAL (L < 2, no terms). */
+syk_status syk_op_to_hamiltonian(const syk_op *a, syk_ham **out);
 
 /* ---------------------------------------------------------------- helpers */
 

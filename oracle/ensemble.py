@@ -70,3 +70,34 @@ def sample_terms(N: int, k: float, seed: int):
         u2 = unit_open1(rng.next())
         J.append(sigma * math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2))
     return subsets, J, sigma
+
+
+def sample_terms_bernoulli(N: int, k: float, seed: int):
+    """The Bernoulli ensemble of Eq. (1): each 4-subset i<j<k<l is kept independently
+    with probability p = k N / C(N,4) (p = 1: the dense model), J ~ N(0, 3!/(p N^3)).
+
+    Draws on one SplitMix64 stream seeded with ``seed``: one uniform (r >> 11) 2^-53 per
+    subset in lexicographic order, kept iff it is below p; then one Box-Muller normal per
+    kept subset, in order.  Returns (subsets, J, sigma)."""
+    if N % 2 or N < 6:
+        raise ValueError("N must be even and >= 6")
+    p = k * N / math.comb(N, 4)
+    if not (0.0 < p <= 1.0):
+        raise ValueError("p out of range")
+    rng = SplitMix64(seed)
+    subsets = []
+    for i in range(N):
+        for j in range(i + 1, N):
+            for kk in range(j + 1, N):
+                for l in range(kk + 1, N):
+                    if unit_open1(rng.next()) < p:
+                        subsets.append((i, j, kk, l))
+    if not subsets:
+        raise ValueError("no term kept")
+    sigma = math.sqrt(6.0 / (p * N ** 3))
+    J = []
+    for _ in subsets:
+        u1 = unit_open0(rng.next())
+        u2 = unit_open1(rng.next())
+        J.append(sigma * math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2))
+    return subsets, J, sigma

@@ -124,3 +124,30 @@ def term_blocks(N: int, subset):
     pU = p % 4
     pD = (p + (2 if top == Z else 0)) % 4
     return (blk, pU), (blk, pD)
+
+
+def from_xz(L: int, x: int, z: int):
+    """The Pauli string X^x Z^z (Z applied first) on L qubits as (labels, p): per qubit
+    X Z = -i Y, so each qubit with both bits set contributes a factor i^-1."""
+    labels = []
+    ny = 0
+    for q in range(L):
+        bx, bz = (x >> q) & 1, (z >> q) & 1
+        if bx and bz:
+            labels.append(Y)
+            ny += 1
+        elif bx:
+            labels.append(X)
+        elif bz:
+            labels.append(Z)
+        else:
+            labels.append(I)
+    return tuple(labels), (-ny) % 4
+
+
+def operator_dense(L: int, xs, zs, cs) -> np.ndarray:
+    """Dense matrix of sum_a c_a X^{x_a} Z^{z_a}."""
+    M = np.zeros((1 << L, 1 << L), dtype=np.complex128)
+    for x, z, c in zip(xs, zs, cs):
+        M += c * dense(from_xz(L, int(x), int(z)))
+    return M

@@ -12,6 +12,8 @@ request engine (Engine: syk_engine_create / submit / poll / cancel / get_stats /
 from ._lib import (  # noqa: F401
     C64,
     C128,
+    EXACT_K,
+    BERNOULLI,
     ECANCELLED,
     EAGAIN,
     Engine,
@@ -19,6 +21,7 @@ from ._lib import (  # noqa: F401
     BLOCK_D,
     SykError,
     Hamiltonian,
+    Operator,
     KrylovOpts,
     apply_H,
     apply_majorana,

@@ -8,6 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libsyk.so")
 
 C64, C128 = 0, 1
+EXACT_K, BERNOULLI = 0, 1
 BLOCK_U, BLOCK_D = 0, 1
 
 STATUS = {0: "SYK_OK", 1: "SYK_EINVAL", 2: "SYK_EUNSUPPORTED", 3: "SYK_ENOMEM", 4: "SYK_EDEVICE",
@@ -107,6 +108,7 @@ _vp, _u64, _i, _d = ct.c_void_p, ct.c_uint64, ct.c_int, ct.c_double
 _dp = ct.POINTER(ct.c_double)
 _SIGS = {
     "syk_create_hamiltonian": [_i, _i, _d, _u64, ct.POINTER(_vp)],
+    "syk_create_hamiltonian_ensemble": [_i, _i, _d, _u64, _i, ct.POINTER(_vp)],
     "syk_destroy_hamiltonian": [_vp],
     "syk_ham_get_info": [_vp, ct.POINTER(HamInfo)],
     "syk_get_terms": [_vp, ct.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -121,6 +123,14 @@ _SIGS = {
     "syk_plan_describe": [_vp, _i, _i, _i, ct.POINTER(PlanDesc)],
     "syk_autotune": [_vp, _i, ct.POINTER(_i), ct.POINTER(ct.c_float), _i, _vp],
     "syk_select_variant": [_vp, _i, _i],
+    "syk_op_create": [_i, ct.c_size_t, _vp, _vp, _dp, _dp, ct.POINTER(_vp)],
+    "syk_op_destroy": [_vp],
+    "syk_op_product": [_vp, _vp, ct.POINTER(_vp)],
+    "syk_op_sum": [_vp, _vp, _d, _d, _d, _d, ct.POINTER(_vp)],
+    "syk_op_adjoint": [_vp, ct.POINTER(_vp)],
+    "syk_op_get_terms": [_vp, ct.c_size_t, ct.POINTER(ct.c_size_t), _vp, _vp, _dp, _dp],
+    "syk_op_is_hermitian": [_vp, ct.POINTER(_i)],
+    "syk_op_to_hamiltonian": [_vp, ct.POINTER(_vp)],
     "syk_otoc_batch": [ct.POINTER(BatchItem), _i, _dp, _i, ct.POINTER(BatchOpts), _dp, _dp, _dp,
                        ct.POINTER(BatchStats), _vp],
     "syk_green": [_vp, _i, _d, _dp, _i, ct.POINTER(OtocOpts), _dp, _dp, _dp, ct.POINTER(OtocStats), _vp],
@@ -180,11 +190,11 @@ def _dtype_of(t):
 
 
 class Hamiltonian:
-    """Owned handle to one disorder realisation (syk_create_hamiltonian)."""
+    """Owned handle to one disorder realisation (syk_create_hamiltonian_ensemble)."""
 
-    def __init__(self, N: int, q: int, k: float, seed: int):
+    def __init__(self, N: int, q: int, k: float, seed: int, ensemble: int = EXACT_K):
         h = _vp()
-        _check(_lib.syk_create_hamiltonian(N, q, float(k), seed, ct.byref(h)))
+        _check(_lib.syk_create_hamiltonian_ensemble(N, q, float(k), seed, ensemble, ct.byref(h)))
         self._h = h
 
     @property
@@ -220,8 +230,10 @@ class Hamiltonian:
             pass
 
 
-def create_hamiltonian(N: int, q: int, k: float, seed: int) -> Hamiltonian:
-    return Hamiltonian(N, q, k, seed)
+def create_hamiltonian(N: int, q: int, k: float, seed: int, ensemble: int = EXACT_K) -> Hamiltonian:
+    """One realisation: ensemble EXACT_K (exactly round(kN) subsets) or BERNOULLI (the
+    paper's B(p) ensemble, p = kN / C(N,4); p = 1 is dense SYK)."""
+    return Hamiltonian(N, q, k, seed, ensemble)
 
 
 def apply_H(ham: Hamiltonian, block: int, x, y, nvec: int = 1, ld: int = None, stream=None):
@@ -451,6 +463,84 @@ class Engine:
     def close(self):
         if self._h:
             _check(_lib.syk_engine_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """General spin operator on L qubits: a sum of Pauli strings c X^x Z^z (Z applied
+    first) held by the library (syk_op_*); products, sums and adjoints are exact."""
+
+    def __init__(self, L: int, x=(), z=(), c=(), _handle=None):
+        if _handle is not None:
+            self._h = _handle
+            self.L = L
+            return
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.uint64))
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.uint64))
+        c = np.asarray(c, dtype=np.complex128)
+        cr = np.ascontiguousarray(c.real)
+        ci = np.ascontiguousarray(c.imag)
+        h = _vp()
+        _check(_lib.syk_op_create(L, x.size, x.ctypes.data, z.ctypes.data, cr.ctypes.data_as(_dp),
+                                  ci.ctypes.data_as(_dp), ct.byref(h)))
+        self._h = h
+        self.L = L
+
+    def _new(self, fn, *args):
+        h = _vp()
+        _check(fn(*args, ct.byref(h)))
+        return Operator(self.L, _handle=h)
+
+    def __matmul__(self, other):
+        return self._new(_lib.syk_op_product, self._h, other._h)
+
+    def __add__(self, other):
+        return self.combine(other, 1.0, 1.0)
+
+    def __sub__(self, other):
+        return self.combine(other, 1.0, -1.0)
+
+    def combine(self, other, alpha: complex, beta: complex):
+        alpha, beta = complex(alpha), complex(beta)
+        return self._new(_lib.syk_op_sum, self._h, other._h, alpha.real, alpha.imag, beta.real, beta.imag)
+
+    def adjoint(self):
+        return self._new(_lib.syk_op_adjoint, self._h)
+
+    def terms(self):
+        """(x, z, c) arrays sorted by (x, z)."""
+        n = ct.c_size_t()
+        _check(_lib.syk_op_get_terms(self._h, 0, ct.byref(n), None, None, None, None))
+        k = n.value
+        x = np.zeros(k, dtype=np.uint64)
+        z = np.zeros(k, dtype=np.uint64)
+        cr, ci = np.zeros(k), np.zeros(k)
+        _check(_lib.syk_op_get_terms(self._h, k, ct.byref(n), x.ctypes.data, z.ctypes.data,
+                                     cr.ctypes.data_as(_dp), ci.ctypes.data_as(_dp)))
+        return x, z, cr + 1j * ci
+
+    def is_hermitian(self) -> bool:
+        v = ct.c_int()
+        _check(_lib.syk_op_is_hermitian(self._h, ct.byref(v)))
+        return bool(v.value)
+
+    def to_hamiltonian(self) -> "Hamiltonian":
+        """A handle for apply_H (either block) and, if Hermitian, krylov_expm."""
+        h = _vp()
+        _check(_lib.syk_op_to_hamiltonian(self._h, ct.byref(h)))
+        ham = Hamiltonian.__new__(Hamiltonian)
+        ham._h = h
+        return ham
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(_lib.syk_op_destroy(self._h))
             self._h = None
 
     def __del__(self):

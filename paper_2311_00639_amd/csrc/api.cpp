@@ -9,6 +9,7 @@
 #include "batch.hpp"
 #include "engine.hpp"
 #include "krylov.hpp"
+#include "op.hpp"
 #include "otoc.hpp"
 
 struct syk_ham {
@@ -17,6 +18,10 @@ struct syk_ham {
 
 struct syk_engine {
     std::unique_ptr<syk::Engine> e;
+};
+
+struct syk_op {
+    syk::Operator op;
 };
 
 namespace {
@@ -63,16 +68,134 @@ void check_N(int N) { require(N % 2 == 0 && N >= 6 && N <= 64, "N must be even w
 
 extern "C" {
 
-syk_status syk_create_hamiltonian(int N, int q, double k, uint64_t seed, syk_ham **out) {
+syk_status syk_create_hamiltonian_ensemble(int N, int q, double k, uint64_t seed, syk_ensemble ensemble,
+                                           syk_ham **out) {
     return guarded([&] {
         require(out != nullptr, "out is NULL");
         *out = nullptr;
         check_N(N);
         if (q != 4) syk::fail(SYK_EUNSUPPORTED, "only q = 4 is defined (Eq. (1))");
         require(std::isfinite(k) && k > 0.0, "k must be positive");
+        require(ensemble == SYK_ENSEMBLE_EXACT_K || ensemble == SYK_ENSEMBLE_BERNOULLI, "unknown ensemble");
         auto *h = new syk_ham();
         try {
-            syk::build_hamiltonian(h->h, N, k, seed);
+            syk::build_hamiltonian(h->h, N, k, seed, ensemble);
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+    });
+}
+
+syk_status syk_create_hamiltonian(int N, int q, double k, uint64_t seed, syk_ham **out) {
+    return syk_create_hamiltonian_ensemble(N, q, k, seed, SYK_ENSEMBLE_EXACT_K, out);
+}
+
+syk_status syk_op_create(int L, size_t n, const uint64_t *x, const uint64_t *z, const double *c_re,
+                         const double *c_im, syk_op **out) {
+    return guarded([&] {
+        require(out != nullptr, "out is NULL");
+        *out = nullptr;
+        require(L >= 1 && L <= 31, "L must lie in [1, 31]");
+        require(n == 0 || (x && z && (c_re || c_im)), "NULL term array");
+        const uint64_t mask = (1ULL << L) - 1ULL;
+        auto *o = new syk_op();
+        o->op.L = L;
+        for (size_t a = 0; a < n; ++a) {
+            if ((x[a] & ~mask) || (z[a] & ~mask)) {
+                delete o;
+                syk::fail(SYK_EINVAL, "Pauli string acts beyond qubit L-1");
+            }
+            const std::complex<double> c(c_re ? c_re[a] : 0.0, c_im ? c_im[a] : 0.0);
+            if (!std::isfinite(c.real()) || !std::isfinite(c.imag())) {
+                delete o;
+                syk::fail(SYK_EINVAL, "non-finite coefficient");
+            }
+            o->op.terms.push_back(syk::OpTerm{x[a], z[a], c});
+        }
+        o->op.canonicalise(0.0);
+        *out = o;
+    });
+}
+
+syk_status syk_op_destroy(syk_op *o) {
+    return guarded([&] { delete o; });
+}
+
+syk_status syk_op_product(const syk_op *a, const syk_op *b, syk_op **out) {
+    return guarded([&] {
+        require(a && b && out, "NULL argument");
+        *out = nullptr;
+        auto *o = new syk_op();
+        try {
+            o->op = syk::op_product(a->op, b->op);
+        } catch (...) {
+            delete o;
+            throw;
+        }
+        *out = o;
+    });
+}
+
+syk_status syk_op_sum(const syk_op *a, const syk_op *b, double alpha_re, double alpha_im, double beta_re,
+                      double beta_im, syk_op **out) {
+    return guarded([&] {
+        require(a && b && out, "NULL argument");
+        *out = nullptr;
+        auto *o = new syk_op();
+        try {
+            o->op = syk::op_sum(a->op, b->op, {alpha_re, alpha_im}, {beta_re, beta_im});
+        } catch (...) {
+            delete o;
+            throw;
+        }
+        *out = o;
+    });
+}
+
+syk_status syk_op_adjoint(const syk_op *a, syk_op **out) {
+    return guarded([&] {
+        require(a && out, "NULL argument");
+        *out = nullptr;
+        auto *o = new syk_op();
+        o->op = syk::op_adjoint(a->op);
+        *out = o;
+    });
+}
+
+syk_status syk_op_get_terms(const syk_op *a, size_t cap, size_t *n, uint64_t *x, uint64_t *z, double *c_re,
+                            double *c_im) {
+    return guarded([&] {
+        require(a && n, "NULL argument");
+        *n = a->op.terms.size();
+        if (!x && !z && !c_re && !c_im) return;
+        require(cap >= a->op.terms.size(), "cap is smaller than the number of terms");
+        for (size_t i = 0; i < a->op.terms.size(); ++i) {
+            const auto &t = a->op.terms[i];
+            if (x) x[i] = t.x;
+            if (z) z[i] = t.z;
+            if (c_re) c_re[i] = t.c.real();
+            if (c_im) c_im[i] = t.c.imag();
+        }
+    });
+}
+
+syk_status syk_op_is_hermitian(const syk_op *a, int *out) {
+    return guarded([&] {
+        require(a && out, "NULL argument");
+        *out = syk::op_is_hermitian(a->op, 1e-13) ? 1 : 0;
+    });
+}
+
+syk_status syk_op_to_hamiltonian(const syk_op *a, syk_ham **out) {
+    return guarded([&] {
+        require(a && out, "NULL argument");
+        *out = nullptr;
+        require(a->op.L >= 2, "apply needs L >= 2 qubits");
+        auto *h = new syk_ham();
+        try {
+            syk::build_operator_hamiltonian(h->h, a->op);
         } catch (...) {
             delete h;
             throw;
@@ -205,6 +328,7 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
                            void *out, uint64_t n_amps, const syk_krylov_opts *o, syk_krylov_stats *stats,
                            void *stream) {
     return guarded([&] {
+        if (h && !h->h.hermitian) syk::fail(SYK_EUNSUPPORTED, "Lanczos propagation needs a Hermitian operator");
         require(h && v && out && o, "NULL argument");
         require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
         require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
@@ -235,6 +359,7 @@ syk_status syk_otoc(const syk_ham *h, int i, int j, double beta, const double *t
                     double *F_raw, double *F_norm, double *F_imag, syk_otoc_stats *stats, void *stream) {
     return guarded([&] {
         require(h && t && o, "NULL argument");
+        if (h->h.ensemble < 0) syk::fail(SYK_EUNSUPPORTED, "the OTOC needs an SYK Hamiltonian (Majorana blocks)");
         syk::check_otoc_args(h->h.N, i, j, beta, t, nt, *o);
         check_device();
         auto t0 = std::chrono::steady_clock::now();
@@ -251,6 +376,7 @@ syk_status syk_green(const syk_ham *h, int n, double beta, const double *t, int 
                      double *G_raw, double *G_norm, double *G_imag, syk_otoc_stats *stats, void *stream) {
     return guarded([&] {
         require(h && t && o, "NULL argument");
+        if (h->h.ensemble < 0) syk::fail(SYK_EUNSUPPORTED, "the Green function needs an SYK Hamiltonian (Majorana blocks)");
         syk::check_otoc_args(h->h.N, n, -1, beta, t, nt, *o, syk::Correlator::Green);
         check_device();
         auto t0 = std::chrono::steady_clock::now();

@@ -109,6 +109,8 @@ struct Hamiltonian {
     int N = 0, L = 0, K = 0;
     double k = 0, p = 0, sigma = 0, sum_J2 = 0;
     uint64_t seed = 0;
+    int ensemble = 0;                  // -1: a general operator (syk_op_to_hamiltonian)
+    bool hermitian = true;
     std::vector<int32_t> ijkl;         // 4K, sorted subsets
     std::vector<double> J;             // K
     std::vector<uint64_t> xmask, zmask;
@@ -132,7 +134,7 @@ struct Hamiltonian {
     ~Hamiltonian();
 };
 
-void build_hamiltonian(Hamiltonian &h, int N, double k, uint64_t seed);
+void build_hamiltonian(Hamiltonian &h, int N, double k, uint64_t seed, int ensemble = SYK_ENSEMBLE_EXACT_K);
 
 // canonical Pauli string i^w X^x Z^z of block Majorana A_n (0 <= n <= N-2) on L qubits
 void block_majorana(int N, int n, uint32_t &x, uint32_t &z, int &w);

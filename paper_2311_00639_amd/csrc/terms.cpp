@@ -1,10 +1,12 @@
 // Host-side construction of one disorder realisation of the sparse SYK Hamiltonian,
 // Eq. (1), and of its parity-block term tables.
 //
-// Coupling ensemble (main text, "Sparse SYK Model"): exactly K = round(kN) distinct
-// 4-subsets drawn uniformly, J ~ N(0, sigma^2) with sigma^2 = 3!/(p N^3), p = K/C(N,4),
-// for chi normalised to {chi_m, chi_n} = delta_mn (the printed 3/(8pN^3) is the variance
-// of J/4, the coefficient of a product of four Pauli-string Majoranas).
+// Coupling ensembles (main text, "Sparse SYK Model"): exactly K = round(kN) distinct
+// 4-subsets drawn uniformly (p = K/C(N,4)), or the paper's Bernoulli ensemble, every
+// 4-subset kept with probability p = k N / C(N,4) (p = 1: dense SYK); J ~ N(0, sigma^2)
+// with sigma^2 = 3!/(p N^3) for chi normalised to {chi_m, chi_n} = delta_mn (the printed
+// 3/(8pN^3) is the variance of J/4, the coefficient of a product of four Pauli-string
+// Majoranas).
 //
 // Term tables: every block Majorana A_n (supplement Eq. (S1), compact form) is a Pauli
 // string i^w X^x Z^z; the product of four of them is formed by
@@ -17,6 +19,7 @@
 #include <cmath>
 #include <set>
 #include <tuple>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -95,32 +98,57 @@ void block_majorana(int N, int n, uint32_t &x, uint32_t &z, int &w) {
     }
 }
 
-void build_hamiltonian(Hamiltonian &h, int N, double k, uint64_t seed) {
+void build_hamiltonian(Hamiltonian &h, int N, double k, uint64_t seed, int ensemble) {
     h.N = N;
     h.L = N / 2 - 1;
     h.k = k;
     h.seed = seed;
     const uint64_t C = choose(N, 4);
-    const double Kd = std::floor(k * static_cast<double>(N) + 0.5);
-    if (!(Kd >= 1.0) || Kd > static_cast<double>(C)) fail(SYK_EINVAL, "K = round(k N) must lie in [1, C(N,4)]");
-    const int K = static_cast<int>(Kd);
-    h.K = K;
-    h.p = static_cast<double>(K) / static_cast<double>(C);
-
     Stream rng{seed};
-    // 2^64 - (2^64 mod C), computed in 64-bit arithmetic: (0 - C) mod C == 2^64 mod C
-    const uint64_t rem = (0ULL - C) % C;
-    const uint64_t limit = 0ULL - rem;           // reject r >= limit (rem == 0: never)
-    std::set<std::tuple<int, int, int, int>> chosen;
-    while (static_cast<int>(chosen.size()) < K) {
-        const uint64_t r = rng.next();
-        if (rem != 0 && r >= limit) continue;
-        chosen.insert(unrank4(r % C));
+    std::vector<std::tuple<int, int, int, int>> chosen;
+    if (ensemble == SYK_ENSEMBLE_BERNOULLI) {
+        // every 4-subset, in lexicographic order, is kept with probability p = k N / C(N,4)
+        // (one draw each, kept iff the [0,1) uniform is below p); p = 1 is the dense model
+        const double p = k * static_cast<double>(N) / static_cast<double>(C);
+        if (!(p > 0.0) || p > 1.0) fail(SYK_EINVAL, "Bernoulli ensemble needs 0 < p = k N / C(N,4) <= 1");
+        for (int i = 0; i < N; ++i)
+            for (int j = i + 1; j < N; ++j)
+                for (int kk = j + 1; kk < N; ++kk)
+                    for (int l = kk + 1; l < N; ++l) {
+                        const double u = static_cast<double>(rng.next() >> 11) * 0x1p-53;
+                        if (u < p) chosen.push_back(std::make_tuple(i, j, kk, l));
+                    }
+        if (chosen.empty()) fail(SYK_EINVAL, "the Bernoulli draw kept no term");
+        h.p = p;
+    } else {
+        const double Kd = std::floor(k * static_cast<double>(N) + 0.5);
+        if (!(Kd >= 1.0) || Kd > static_cast<double>(C)) fail(SYK_EINVAL, "K = round(k N) must lie in [1, C(N,4)]");
+        const int Kt = static_cast<int>(Kd);
+        // 2^64 - (2^64 mod C), computed in 64-bit arithmetic: (0 - C) mod C == 2^64 mod C
+        const uint64_t rem = (0ULL - C) % C;
+        const uint64_t limit = 0ULL - rem;           // reject r >= limit (rem == 0: never)
+        std::set<std::tuple<int, int, int, int>> set;
+        while (static_cast<int>(set.size()) < Kt) {
+            const uint64_t r = rng.next();
+            if (rem != 0 && r >= limit) continue;
+            set.insert(unrank4(r % C));
+        }
+        chosen.assign(set.begin(), set.end());       // std::set iterates in lexicographic order
+        h.p = static_cast<double>(Kt) / static_cast<double>(C);
     }
+    const int K = static_cast<int>(chosen.size());
+    h.K = K;
+    h.ensemble = ensemble;
 
-    const double num = 6.0 * static_cast<double>(C);
-    const double den = static_cast<double>(K) * static_cast<double>(N * N * N);
+    // sigma^2 = 3! / (p N^3)
+    const double num = 6.0;
+    const double den = h.p * static_cast<double>(N * N * N);
     h.sigma = std::sqrt(num / den);
+    if (ensemble != SYK_ENSEMBLE_BERNOULLI) {        // the exact-K form, kept bit-for-bit
+        const double num_c = 6.0 * static_cast<double>(C);
+        const double den_c = static_cast<double>(K) * static_cast<double>(N * N * N);
+        h.sigma = std::sqrt(num_c / den_c);
+    }
     const double two_pi = 2.0 * M_PI;
 
     h.ijkl.clear();
@@ -130,7 +158,7 @@ void build_hamiltonian(Hamiltonian &h, int N, double k, uint64_t seed) {
     h.phase[0].clear();
     h.phase[1].clear();
     h.sum_J2 = 0.0;
-    for (const auto &t : chosen) {       // std::set iterates in lexicographic order
+    for (const auto &t : chosen) {
         h.ijkl.push_back(std::get<0>(t));
         h.ijkl.push_back(std::get<1>(t));
         h.ijkl.push_back(std::get<2>(t));

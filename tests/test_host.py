@@ -167,3 +167,61 @@ def test_plan_describe_every_variant_N56(dt):
         for tpw, p in m.items():
             if tpw > 1:
                 assert p < m.get(1, 1e9)
+
+
+@pytest.mark.parametrize("N,k,seed", [(12, 5.0, 3), (16, 4.0, 7), (16, 1820 / 16, 1), (20, 2.5, 9)])
+def test_bernoulli_tables_match_oracle_bitwise(N, k, seed):
+    """The library's Bernoulli draw (subsets, J, sigma, K) equals the oracle's bit for bit."""
+    h = syk.create_hamiltonian(N, 4, k, seed, syk.BERNOULLI)
+    T = h.terms()
+    subs, J, sigma = ensemble.sample_terms_bernoulli(N, k, seed)
+    assert h.info()["K"] == len(subs)
+    assert np.array_equal(T["ijkl"], np.asarray(subs, dtype=np.int32))
+    assert np.array_equal(T["J"], np.asarray(J)) and h.info()["sigma"] == sigma
+
+
+def test_bernoulli_argument_errors():
+    for args in [(16, 4, 200.0, 1, syk.BERNOULLI), (16, 4, 2.0, 1, 7)]:
+        with pytest.raises(syk.SykError) as e:
+            syk.create_hamiltonian(*args)
+        assert e.value.status == 1
+
+
+def _random_op(L, n, rng):
+    x = rng.integers(0, 1 << L, n).astype(np.uint64)
+    z = rng.integers(0, 1 << L, n).astype(np.uint64)
+    c = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return x, z, c
+
+
+def test_operator_algebra_matches_dense():
+    """Products, linear combinations and adjoints of Pauli sums (host) equal the dense
+    matrix operations of the oracle's Kronecker-built matrices."""
+    rng = np.random.default_rng(21)
+    L = 4
+    xa, za, ca = _random_op(L, 7, rng)
+    xb, zb, cb = _random_op(L, 5, rng)
+    A = syk.Operator(L, xa, za, ca)
+    B = syk.Operator(L, xb, zb, cb)
+    dA = pauli.operator_dense(L, xa, za, ca)
+    dB = pauli.operator_dense(L, xb, zb, cb)
+    dense_of = lambda op: pauli.operator_dense(L, *op.terms())
+    assert np.allclose(dense_of(A), dA, atol=1e-13)
+    assert np.allclose(dense_of(A @ B), dA @ dB, atol=1e-12)
+    assert np.allclose(dense_of(A.combine(B, 0.5 - 2j, 3.0)), (0.5 - 2j) * dA + 3.0 * dB, atol=1e-12)
+    assert np.allclose(dense_of(A.adjoint()), dA.conj().T, atol=1e-13)
+    H = A + A.adjoint()
+    assert H.is_hermitian() and not A.is_hermitian()
+    # merged terms: A - A has no terms
+    assert (A - A).terms()[0].size == 0
+
+
+def test_operator_argument_errors():
+    with pytest.raises(syk.SykError):
+        syk.Operator(3, [8], [0], [1.0])           # beyond qubit L-1
+    with pytest.raises(syk.SykError):
+        syk.Operator(0, [], [], [])
+    with pytest.raises(syk.SykError):
+        syk.Operator(3, [1], [0], [float("nan")])
+    with pytest.raises(syk.SykError):
+        syk.Operator(3, [1], [0], [1.0]) @ syk.Operator(4, [1], [0], [1.0])

@@ -5,6 +5,7 @@ identity the paper states, a closed form, a library routine, a hand-derived fixt
 or a statistical law.  A plausible mistake (dropped term, wrong sign or index,
 transposed operand) in the oracle fails at least one of them.
 """
+import itertools
 import math
 import os
 
@@ -431,3 +432,64 @@ def test_matfree_hermitian_at_large_N():
             f = lambda idx, k=m: (idx == k).astype(np.complex128)
             hnm = matfree.apply_rows(terms, f, np.array([n], dtype=np.uint64))[0]
             assert abs(hmn - np.conj(hnm)) < 1e-15
+
+
+# --------------------------------------------------------------------------- Bernoulli ensemble
+def test_bernoulli_dense_limit_keeps_every_subset():
+    """p = 1 (k = C(N,4)/N) is the dense model: every 4-subset, in lexicographic order."""
+    N = 10
+    subs, J, sigma = ensemble.sample_terms_bernoulli(N, math.comb(N, 4) / N, 3)
+    assert subs == list(itertools.combinations(range(N), 4))
+    assert abs(sigma - math.sqrt(6.0 / N ** 3)) < 1e-15 and len(J) == len(subs)
+
+
+def test_bernoulli_counts_and_coupling_moments():
+    """K ~ Binomial(C(N,4), p) with p = kN / C(N,4); J ~ N(0, 3!/(p N^3))."""
+    N, k = 14, 3.0
+    C = math.comb(N, 4)
+    p = k * N / C
+    Ks, Js = [], []
+    for seed in range(60):
+        subs, J, sigma = ensemble.sample_terms_bernoulli(N, k, 1000 + seed)
+        assert subs == sorted(set(subs)) and all(s[0] < s[1] < s[2] < s[3] < N for s in subs)
+        Ks.append(len(subs))
+        Js.extend(np.asarray(J) / sigma)
+    mean, sd = C * p, math.sqrt(C * p * (1 - p))
+    assert abs(np.mean(Ks) - mean) < 4 * sd / math.sqrt(len(Ks))
+    assert abs(np.std(Ks) / sd - 1) < 0.35
+    Js = np.asarray(Js)
+    assert abs(Js.mean()) < 4 / math.sqrt(Js.size) and abs(Js.var() - 1) < 6 * math.sqrt(2 / Js.size)
+    assert abs(sigma ** 2 * p * N ** 3 - 6.0) < 1e-12
+
+
+def test_bernoulli_hamiltonian_invariants():
+    N = 12
+    subs, J, _ = ensemble.sample_terms_bernoulli(N, 6.0, 11)
+    H = dense.hamiltonian(N, subs, J)
+    d = H.shape[0]
+    assert np.allclose(H, H.conj().T, atol=1e-14)
+    assert abs(np.trace(H)) < 1e-12
+    assert abs(np.trace(H @ H).real / d - np.sum(np.asarray(J) ** 2) / 16) < 1e-12
+
+
+# --------------------------------------------------------------------------- spin operators
+def test_from_xz_round_trip_and_textbook_products():
+    """X^x Z^z from per-qubit labels: canonical() inverts it, and on one qubit X Z = -i Y
+    is the product of the textbook matrices."""
+    rng = np.random.default_rng(4)
+    for _ in range(40):
+        L = int(rng.integers(1, 7))
+        x, z = int(rng.integers(0, 1 << L)), int(rng.integers(0, 1 << L))
+        assert pauli.canonical(pauli.from_xz(L, x, z)) == (x, z, 0)
+    Xm, Zm = pauli.SIGMA[pauli.X], pauli.SIGMA[pauli.Z]
+    assert np.allclose(pauli.dense(pauli.from_xz(1, 1, 1)), Xm @ Zm)
+    # two qubits: X^x Z^z = (X^x1 Z^z1) (x) (X^x0 Z^z0), qubit 1 the most significant
+    M = pauli.dense(pauli.from_xz(2, 0b01, 0b11))
+    assert np.allclose(M, np.kron(Zm, Xm @ Zm))
+
+
+def test_operator_dense_is_linear():
+    L = 3
+    a = pauli.operator_dense(L, [1, 6], [2, 5], [0.5, -1j])
+    b = pauli.operator_dense(L, [1], [2], [0.5]) + pauli.operator_dense(L, [6], [5], [-1j])
+    assert np.allclose(a, b)
