@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.linalg
 
-from oracle import dense, ensemble, haar, matfree, pauli, splitmix
+from oracle import dense, ensemble, haar, lyapunov, matfree, pauli, splitmix
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -493,3 +493,133 @@ def test_operator_dense_is_linear():
     a = pauli.operator_dense(L, [1, 6], [2, 5], [0.5, -1j])
     b = pauli.operator_dense(L, [1], [2], [0.5]) + pauli.operator_dense(L, [6], [5], [-1j])
     assert np.allclose(a, b)
+
+
+# ---------------------------------------------------------------- t*(N) and lambda_L
+
+def test_crossing_time_piecewise_linear_is_exact():
+    t = [0.0, 1.0, 2.0, 3.0]
+    F = [1.0, 0.9, 0.7, 0.4]
+    assert lyapunov.crossing_time(t, F, 0.8)[0] == pytest.approx(1.5, abs=1e-15)
+    assert lyapunov.crossing_time(t, F, 0.85)[0] == pytest.approx(1.25, abs=1e-15)
+    assert lyapunov.crossing_time(t, F, 0.9)[0] == 1.0           # a sample equal to F0
+    assert math.isnan(lyapunov.crossing_time(t, F, 0.3)[0])      # never reached
+    # the first crossing counts, not a later one after a revival
+    assert lyapunov.crossing_time([0, 1, 2, 3, 4], [1.0, 0.7, 0.9, 0.6, 0.5], 0.8)[0] == pytest.approx(0.6667, abs=1e-4)
+
+
+def test_crossing_time_error_of_a_straight_line():
+    # F = 1 - s t with a constant standard error: sigma_t = sigma_F / s
+    s, sig = 0.2, 0.01
+    t = np.linspace(0.0, 3.0, 7)
+    ts, err = lyapunov.crossing_time(t, 1.0 - s * t, 0.75, np.full(7, sig))
+    assert ts == pytest.approx(1.25, abs=1e-14) and err == pytest.approx(sig / s, rel=1e-14)
+
+
+def test_crossing_time_on_a_smooth_curve_within_interpolation_bound():
+    # F = 1 - c1 e^{lam t}/N is concave, so the chord lies below it and crosses F0 first;
+    # the time error is at most (h^2/8) max|F''| / min|F'| over the bracketing segment
+    lam, c1, N, F0 = 1.1, 0.3, 30.0, 0.8
+    exact = (math.log(N) + math.log((1 - F0) / c1)) / lam
+    for h in (0.1, 0.05, 0.025, 0.0125):
+        t = np.arange(0.0, 6.0 + h / 2, h)
+        err = lyapunov.crossing_time(t, 1 - c1 * np.exp(lam * t) / N, F0)[0] - exact
+        lo = math.floor(exact / h) * h
+        bound = h * h / 8 * c1 * lam ** 2 * math.exp(lam * (lo + h)) / N / (c1 * lam * math.exp(lam * lo) / N)
+        assert -bound <= err <= 0.0, (h, err, bound)
+
+
+def test_inverse_slope_of_pure_logarithm_is_lambda():
+    # t* = gamma_0 + log N / lambda: the log difference quotient gives lambda exactly
+    lam, g0 = 0.73, -1.2
+    N = np.array([14.0, 22.0, 30.0, 38.0, 46.0, 54.0])
+    Nm, y, e = lyapunov.slope_points(N, g0 + np.log(N) / lam)
+    assert np.allclose(y, lam, rtol=1e-13) and np.all(np.isnan(e))
+    assert np.allclose(Nm, np.sqrt(N[:-1] * N[1:]))
+    Nm4, _, _ = lyapunov.slope_points(N, g0 + np.log(N) / lam, dN=16)
+    assert len(Nm4) == 4
+    assert len(lyapunov.slope_points([14.0, 30.0], [1.0, 2.0])[0]) == 0   # no pair 8 apart
+
+
+def test_fit_slope_two_parameters_matches_textbook_regression():
+    rng = np.random.default_rng(4)
+    x = 1.0 / np.array([17.0, 25.7, 33.8, 41.8, 49.8])
+    sig = rng.uniform(0.01, 0.05, x.size)
+    y = 0.8 - 3.0 * x + sig * rng.standard_normal(x.size)
+    w = 1 / sig ** 2
+    S, Sx, Sy, Sxx, Sxy = w.sum(), (w * x).sum(), (w * y).sum(), (w * x * x).sum(), (w * x * y).sum()
+    D = S * Sxx - Sx ** 2
+    r = lyapunov.fit_slope(1.0 / x, y, sig, a1=True, a2=False)
+    assert r["lambda"] == pytest.approx((Sxx * Sy - Sx * Sxy) / D, rel=1e-12)
+    assert r["alpha1"] == pytest.approx((S * Sxy - Sx * Sy) / D, rel=1e-12)
+    assert r["lambda_err"] == pytest.approx(math.sqrt(Sxx / D), rel=1e-12)
+    assert r["alpha1_err"] == pytest.approx(math.sqrt(S / D), rel=1e-12)
+    assert r["dof"] == 3 and r["alpha2"] == 0.0
+
+
+def test_fit_slope_constant_is_weighted_mean():
+    y = np.array([0.7, 0.9, 0.8])
+    sig = np.array([0.1, 0.2, 0.05])
+    r = lyapunov.fit_slope([20.0, 30.0, 40.0], y, sig, a1=False)
+    w = 1 / sig ** 2
+    assert r["lambda"] == pytest.approx((w * y).sum() / w.sum(), rel=1e-13)
+    assert r["lambda_err"] == pytest.approx(1 / math.sqrt(w.sum()), rel=1e-13)
+    ru = lyapunov.fit_slope([20.0, 30.0, 40.0], y, None, a1=False)
+    assert ru["lambda"] == pytest.approx(0.8, rel=1e-14)
+    assert ru["lambda_err"] == pytest.approx(y.std(ddof=1) / math.sqrt(3), rel=1e-12)
+
+
+@pytest.mark.parametrize("g1,g2", [(True, False), (False, True), (True, True)])
+def test_fit_global_recovers_model_parameters(g1, g2):
+    lam, g0, c1, c2 = 0.62, -0.9, 3.5 if g1 else 0.0, -40.0 if g2 else 0.0
+    N = np.array([14.0, 22.0, 30.0, 38.0, 46.0, 54.0])
+    ts = g0 + np.log(N) / lam * (1 + c1 / N + c2 / N ** 2)
+    r = lyapunov.fit_global(N, ts, None, g1=g1, g2=g2)
+    assert r["lambda"] == pytest.approx(lam, rel=1e-9) and r["gamma0"] == pytest.approx(g0, abs=1e-8)
+    assert r["gamma1"] == pytest.approx(c1, abs=1e-6) and r["gamma2"] == pytest.approx(c2, abs=1e-4)
+
+
+def test_fit_global_matches_nonlinear_least_squares():
+    # the linear reparametrisation has the same optimum and, by first-order propagation,
+    # the same covariance as a direct non-linear fit in (gamma_0, lambda, gamma_1)
+    import scipy.optimize
+    rng = np.random.default_rng(9)
+    N = np.array([14.0, 22.0, 30.0, 38.0, 46.0, 54.0])
+    sig = rng.uniform(0.02, 0.06, N.size)
+    ts = -0.5 + np.log(N) / 0.7 * (1 + 2.0 / N) + sig * rng.standard_normal(N.size)
+    r = lyapunov.fit_global(N, ts, sig, g1=True)
+    f = lambda n, a, lam, c: a + np.log(n) / lam * (1 + c / n)            # noqa: E731
+    p, cov = scipy.optimize.curve_fit(f, N, ts, p0=[0.0, 0.5, 0.0], sigma=sig, absolute_sigma=True,
+                                     xtol=1e-15, ftol=1e-15, gtol=1e-15)
+    e = np.sqrt(np.diag(cov))
+    assert r["gamma0"] == pytest.approx(p[0], abs=1e-6) and r["lambda"] == pytest.approx(p[1], rel=1e-6)
+    assert r["gamma1"] == pytest.approx(p[2], abs=1e-5)
+    assert r["lambda_err"] == pytest.approx(e[1], rel=1e-4) and r["gamma1_err"] == pytest.approx(e[2], rel=1e-4)
+    assert r["gamma0_err"] == pytest.approx(e[0], rel=1e-4)
+    chi2 = float((((ts - f(N, *p)) / sig) ** 2).sum())
+    assert r["chi2"] == pytest.approx(chi2, rel=1e-6)
+
+
+def test_lyapunov_chain_on_curves_with_the_scaling_form():
+    # F_N(t) = 1 - c1 e^{lambda t} / N (the form of Eqs. (3)-(4) with g0 = 1, g linear):
+    # t*(N) = (log N + log((1 - F0)/c1)) / lambda, so both fits return lambda
+    lam, c1 = 0.9, 0.25
+    t = np.arange(0.0, 8.0, 0.01)
+    N = np.array([14.0, 22.0, 30.0, 38.0, 46.0, 54.0])
+    for F0 in (0.75, 0.85):
+        ts = np.array([lyapunov.crossing_time(t, 1 - c1 * np.exp(lam * t) / n, F0)[0] for n in N])
+        assert np.allclose(ts, (np.log(N) + math.log((1 - F0) / c1)) / lam, atol=2e-5)
+        Nm, y, _ = lyapunov.slope_points(N, ts)
+        assert lyapunov.fit_slope(Nm, y)["lambda"] == pytest.approx(lam, rel=1e-3)
+        g = lyapunov.fit_global(N, ts, g1=False)
+        assert g["lambda"] == pytest.approx(lam, rel=1e-4)
+        assert g["gamma0"] == pytest.approx(math.log((1 - F0) / c1) / lam, abs=1e-3)
+
+
+def test_ensemble_mean_and_standard_error():
+    import scipy.stats
+    rng = np.random.default_rng(2)
+    rows = 1 + 0.1 * rng.standard_normal((7, 5))
+    m, s = lyapunov.ensemble_mean(rows)
+    assert np.allclose(m, rows.mean(axis=0)) and np.allclose(s, scipy.stats.sem(rows, axis=0), rtol=1e-13)
+    assert np.all(lyapunov.ensemble_mean(rows[:1])[1] == 0.0)
