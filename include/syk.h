@@ -240,6 +240,7 @@ typedef struct {
     uint64_t seed;         /* realisation (syk_create_hamiltonian) */
     int i, j;              /* W = chi_i, V = chi_j, distinct, in [0, N) */
     uint64_t state_seed;
+    int ensemble;          /* syk_ensemble of the realisation (0 = SYK_ENSEMBLE_EXACT_K) */
 } syk_batch_item;
 
 typedef struct {
@@ -266,6 +267,88 @@ typedef struct {
 syk_status syk_otoc_batch(const syk_batch_item *items, int n_items, const double *t, int nt,
                           const syk_batch_opts *o, double *F_raw, double *F_norm, double *F_imag,
                           syk_batch_stats *stats, void *stream);
+
+/* ---------------------------------------------------------------- t*(N) and lambda_L */
+/* Disorder average of the normalised OTOC of Eq. (2) over n_real realisations: realisation
+ * r (0-based) is the Hamiltonian syk_create_hamiltonian_ensemble(N, 4, k, seed + r,
+ * ensemble) with Haar vectors syk_haar_state(N, o->state_seed + r, v), v < o->nvec; its
+ * curve is normalised by its own F(0) (the F_norm of syk_otoc), and the curves are then
+ * averaged.  This averaged curve is the one whose crossing of F0 defines t*(N) (main text,
+ * before Eq. (4)).  Path: the batched persistent launch of syk_otoc_batch (complex64
+ * states; 18 <= N <= 32; m <= 60; profile = 0) or the single-request path of syk_otoc, one
+ * realisation after the other, in o->dtype. */
+typedef struct {
+    int N;                 /* Majoranas (even) */
+    double k;              /* sparsity (as syk_create_hamiltonian_ensemble) */
+    int ensemble;          /* syk_ensemble */
+    uint64_t seed;         /* realisation r uses seed + r */
+    int n_real;            /* realisations (>= 1) */
+    int i, j;              /* W = chi_i, V = chi_j (the paper: N-1, N-2) */
+    double beta;
+    int path;              /* -1: batched when it serves the request, 0: batched (EUNSUPPORTED
+                              if it cannot), 1: single-request path */
+} syk_ensemble_desc;
+
+typedef struct {
+    int path;              /* 0 batched, 1 single-request */
+    long long matvecs;
+    double seconds;
+} syk_ensemble_stats;
+
+/* t: host, nt non-decreasing times >= 0.  Outputs (host; any may be NULL): F_mean[n] and
+ * F_sem[n] (nt doubles), the mean over realisations of the normalised curves and its
+ * standard error (sample standard deviation / sqrt(n_real); 0 when n_real = 1); F_rows
+ * (n_real x nt doubles, row r = realisation r), every normalised curve.  Options o as for
+ * syk_otoc (nvec, state_seed, dtype, krylov; the batched path takes nvec, m, tol and
+ * max_substeps from it).  Synchronises `stream`.  Errors: EINVAL, EUNSUPPORTED, ENOMEM,
+ * EDEVICE, ENOTCONV, ENUMERIC. */
+syk_status syk_otoc_ensemble(const syk_ensemble_desc *d, const double *t, int nt, const syk_otoc_opts *o,
+                             double *F_mean, double *F_sem, double *F_rows, syk_ensemble_stats *stats,
+                             void *stream);
+
+/* Crossing time t* of a sampled curve (main text, before Eq. (4)): the first n >= 1 with
+ * F[n] <= F0 < F[n-1], then linear interpolation between samples n-1 and n.  F_err (host,
+ * nt, may be NULL) are standard errors of the samples; *tstar_err (may be NULL) receives
+ * sigma_F(t*) / |dF/dt| with sigma_F interpolated linearly and the slope of the bracketing
+ * segment (NaN without F_err).  A curve that never falls to F0 gives *tstar = NaN and
+ * SYK_OK.  Host only.  Errors: EINVAL (nt < 2, t decreasing, non-finite F0). */
+syk_status syk_crossing_time(const double *t, const double *F, const double *F_err, int nt, double F0,
+                             double *tstar, double *tstar_err);
+
+typedef enum {
+    SYK_FIT_SLOPE = 0,     /* Eq. (5): 1/(N dt* / dN) = lambda + alpha_1/N + alpha_2/N^2 */
+    SYK_FIT_GLOBAL = 1     /* Eq. (6): t* = gamma_0 + (log N/lambda)(1 + gamma_1/N + gamma_2/N^2) */
+} syk_fit_method;
+
+typedef struct {
+    int method;            /* syk_fit_method */
+    int terms;             /* bit 0: the 1/N term (alpha_1 or gamma_1), bit 1: the 1/N^2 term */
+    int dN;                /* SYK_FIT_SLOPE: N is paired with N + dN (the supplement: 8) */
+} syk_fit_opts;
+
+typedef struct {
+    double lambda, lambda_err;
+    double coef[3], coef_err[3];   /* SLOPE: alpha_1, alpha_2, 0; GLOBAL: gamma_0, gamma_1,
+                                      gamma_2 (terms left out: 0, error 0) */
+    double chi2;           /* weighted residual sum of squares (unweighted without errors) */
+    int n_points, dof;     /* points fitted (SLOPE: pairs), n_points - parameters */
+} syk_fit_result;
+
+/* Lyapunov exponent from crossing times t*(N) (host, n values each; N need not be sorted).
+ * SYK_FIT_SLOPE: every pair (N_a, N_b = N_a + dN) gives the inverse slope
+ * y = log(N_b/N_a) / (t*_b - t*_a) (a central difference in log N) at sqrt(N_a N_b), with
+ * error |y| sqrt(s_a^2 + s_b^2) / |t*_b - t*_a| (supplement Sec. II.A); the pairs are fitted
+ * by Eq. (5).  SYK_FIT_GLOBAL: t* is fitted by Eq. (6), solved as the linear problem in
+ * (gamma_0, 1/lambda, gamma_1/lambda, gamma_2/lambda) with first-order error propagation.
+ * With tstar_err (host, n, may be NULL) the fit is weighted by 1/sigma^2 and the errors are
+ * the absolute ones, (A^T W A)^{-1}; without, it is unweighted and the covariance is scaled
+ * by chi2/dof (errors NaN when dof = 0).  pts_N, pts_y, pts_err (host, cap entries, may be
+ * NULL): the fitted points (SLOPE: N_mid, y, error; GLOBAL: N, t*, error).  Host only.
+ * Errors: EINVAL (non-finite input, fewer points than parameters, dependent columns, equal
+ * t* for a pair, cap below n_points). */
+syk_status syk_lyapunov_fit(const double *N, const double *tstar, const double *tstar_err, int n,
+                            const syk_fit_opts *o, syk_fit_result *out, double *pts_N, double *pts_y,
+                            double *pts_err, int cap);
 
 /* ---------------------------------------------------------------- request engine */
 /* Serving engine: OTOC requests of mixed N, k and seed (one disorder realisation each,

@@ -7,7 +7,9 @@ Python or CPU fallback: if the library is missing, importing the binding raises.
 
 Names follow the C ABI in ``include/syk.h``: create_hamiltonian, apply_H,
 haar_state, apply_majorana, krylov_expm, otoc, workspace_bytes, tridiag_expm, and the
-request engine (Engine: syk_engine_create / submit / poll / cancel / get_stats / destroy).
+request engine (Engine: syk_engine_create / submit / poll / cancel / get_stats / destroy),
+the disorder average otoc_ensemble and the finite-size-scaling analysis crossing_time and
+lyapunov_fit.
 """
 from ._lib import (  # noqa: F401
     C64,
@@ -16,6 +18,8 @@ from ._lib import (  # noqa: F401
     BERNOULLI,
     ECANCELLED,
     EAGAIN,
+    FIT_GLOBAL,
+    FIT_SLOPE,
     Engine,
     BLOCK_U,
     BLOCK_D,
@@ -27,13 +31,16 @@ from ._lib import (  # noqa: F401
     apply_majorana,
     autotune,
     create_hamiltonian,
+    crossing_time,
     green,
     haar_state,
     kernel_revision,
     krylov_expm,
     library_path,
+    lyapunov_fit,
     otoc,
     otoc_batch,
+    otoc_ensemble,
     plan_describe,
     release_workspace,
     select_variant,

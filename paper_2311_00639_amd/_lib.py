@@ -91,7 +91,7 @@ class EngineStats(ct.Structure):
 
 class BatchItem(ct.Structure):
     _fields_ = [("N", ct.c_int), ("k", ct.c_double), ("seed", ct.c_uint64), ("i", ct.c_int), ("j", ct.c_int),
-                ("state_seed", ct.c_uint64)]
+                ("state_seed", ct.c_uint64), ("ensemble", ct.c_int)]
 
 
 class BatchOpts(ct.Structure):
@@ -103,6 +103,26 @@ class BatchStats(ct.Structure):
     _fields_ = [("matvecs", ct.c_longlong), ("n_jobs", ct.c_int), ("slots", ct.c_int), ("variant", ct.c_int),
                 ("kernel_ms", ct.c_double), ("tuned_ms", ct.c_double * 3), ("seconds", ct.c_double)]
 
+
+class EnsembleDesc(ct.Structure):
+    _fields_ = [("N", ct.c_int), ("k", ct.c_double), ("ensemble", ct.c_int), ("seed", ct.c_uint64),
+                ("n_real", ct.c_int), ("i", ct.c_int), ("j", ct.c_int), ("beta", ct.c_double), ("path", ct.c_int)]
+
+
+class EnsembleStats(ct.Structure):
+    _fields_ = [("path", ct.c_int), ("matvecs", ct.c_longlong), ("seconds", ct.c_double)]
+
+
+class FitOpts(ct.Structure):
+    _fields_ = [("method", ct.c_int), ("terms", ct.c_int), ("dN", ct.c_int)]
+
+
+class FitResult(ct.Structure):
+    _fields_ = [("lambda_", ct.c_double), ("lambda_err", ct.c_double), ("coef", ct.c_double * 3),
+                ("coef_err", ct.c_double * 3), ("chi2", ct.c_double), ("n_points", ct.c_int), ("dof", ct.c_int)]
+
+
+FIT_SLOPE, FIT_GLOBAL = 0, 1
 
 _vp, _u64, _i, _d = ct.c_void_p, ct.c_uint64, ct.c_int, ct.c_double
 _dp = ct.POINTER(ct.c_double)
@@ -134,6 +154,10 @@ _SIGS = {
     "syk_otoc_batch": [ct.POINTER(BatchItem), _i, _dp, _i, ct.POINTER(BatchOpts), _dp, _dp, _dp,
                        ct.POINTER(BatchStats), _vp],
     "syk_green": [_vp, _i, _d, _dp, _i, ct.POINTER(OtocOpts), _dp, _dp, _dp, ct.POINTER(OtocStats), _vp],
+    "syk_otoc_ensemble": [ct.POINTER(EnsembleDesc), _dp, _i, ct.POINTER(OtocOpts), _dp, _dp, _dp,
+                          ct.POINTER(EnsembleStats), _vp],
+    "syk_crossing_time": [_dp, _dp, _dp, _i, _d, _dp, _dp],
+    "syk_lyapunov_fit": [_dp, _dp, _dp, _i, ct.POINTER(FitOpts), ct.POINTER(FitResult), _dp, _dp, _dp, _i],
     "syk_engine_create": [ct.POINTER(EngineOpts), ct.POINTER(_vp)],
     "syk_engine_submit": [_vp, ct.POINTER(Request), ct.POINTER(_u64)],
     "syk_engine_poll": [_vp, _i, ct.POINTER(ResultInfo), _dp, _dp, _dp, _i],
@@ -348,13 +372,14 @@ def green(ham: Hamiltonian, n: int, beta: float, t, nvec: int = 1, state_seed: i
 
 def otoc_batch(items, beta: float, t, nvec: int = 1, m: int = 30, tol: float = 1e-7, variant: int = -1,
                max_substeps: int = 0, stream=None):
-    """Batched OTOC (syk_otoc_batch).  items: sequence of (N, k, seed, i, j, state_seed).
-    Returns (F_raw, F_norm, F_imag, stats) with arrays of shape (len(items), len(t))."""
+    """Batched OTOC (syk_otoc_batch).  items: sequence of (N, k, seed, i, j, state_seed) or
+    (N, k, seed, i, j, state_seed, ensemble).  Returns (F_raw, F_norm, F_imag, stats) with
+    arrays of shape (len(items), len(t))."""
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
     nt = t.size
     n = len(items)
-    arr = (BatchItem * n)(*[BatchItem(int(N), float(k), int(seed), int(i), int(j), int(ss))
-                            for (N, k, seed, i, j, ss) in items])
+    arr = (BatchItem * n)(*[BatchItem(int(it[0]), float(it[1]), int(it[2]), int(it[3]), int(it[4]), int(it[5]),
+                                      int(it[6]) if len(it) > 6 else EXACT_K) for it in items])
     o = BatchOpts(nvec, float(beta), m, float(tol), variant, max_substeps)
     raw, nrm, im = np.zeros((n, nt)), np.zeros((n, nt)), np.zeros((n, nt))
     st = BatchStats()
@@ -364,6 +389,77 @@ def otoc_batch(items, beta: float, t, nvec: int = 1, m: int = 30, tol: float = 1
     out = {f: getattr(st, f) for f, _ in BatchStats._fields_ if f != "tuned_ms"}
     out["tuned_ms"] = list(st.tuned_ms)
     return raw, nrm, im, out
+
+
+def otoc_ensemble(N: int, k: float, seed: int, n_real: int, i: int, j: int, beta: float, t, ensemble: int = EXACT_K,
+                  nvec: int = 1, state_seed: int = 0, dtype: int = C64, m: int = None, tol: float = None,
+                  path: int = -1, rows: bool = False, stream=None):
+    """Disorder-averaged normalised OTOC (syk_otoc_ensemble).  Returns (F_mean, F_sem, stats),
+    plus the per-realisation curves (n_real x nt) when rows is true."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    nt = t.size
+    d = EnsembleDesc(int(N), float(k), int(ensemble), int(seed), int(n_real), int(i), int(j), float(beta), int(path))
+    o = OtocOpts()
+    o.nvec = nvec
+    o.state_seed = state_seed
+    o.dtype = dtype
+    o.krylov = default_krylov_opts(dtype)
+    o.layout = -1
+    o.autotune = 0
+    if m is not None:
+        o.krylov.m = m
+    if tol is not None:
+        o.krylov.tol = tol
+    mean, sem = np.zeros(nt), np.zeros(nt)
+    R = np.zeros((n_real, nt)) if rows else None
+    st = EnsembleStats()
+    dp = lambda a: None if a is None else a.ctypes.data_as(_dp)
+    _check(_lib.syk_otoc_ensemble(ct.byref(d), dp(t), nt, ct.byref(o), dp(mean), dp(sem), dp(R), ct.byref(st),
+                                  _stream(stream)))
+    out = {f: getattr(st, f) for f, _ in EnsembleStats._fields_}
+    return (mean, sem, out, R) if rows else (mean, sem, out)
+
+
+def crossing_time(t, F, F0: float, F_err=None):
+    """syk_crossing_time: (t*, sigma_t*); t* is nan when the curve never falls to F0."""
+    t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
+    F = np.ascontiguousarray(np.asarray(F, dtype=np.float64))
+    if F.size != t.size:
+        raise ValueError("t and F differ in length")
+    e = None if F_err is None else np.ascontiguousarray(np.asarray(F_err, dtype=np.float64))
+    if e is not None and e.size != t.size:
+        raise ValueError("t and F_err differ in length")
+    ts, err = ct.c_double(), ct.c_double()
+    dp = lambda a: None if a is None else a.ctypes.data_as(_dp)
+    _check(_lib.syk_crossing_time(dp(t), dp(F), dp(e), t.size, float(F0), ct.byref(ts), ct.byref(err)))
+    return ts.value, err.value
+
+
+def lyapunov_fit(N, tstar, tstar_err=None, method: int = FIT_SLOPE, terms: int = 1, dN: int = 8) -> dict:
+    """syk_lyapunov_fit: lambda and the correction coefficients of Eq. (5) (method FIT_SLOPE:
+    alpha1, alpha2) or Eq. (6) (FIT_GLOBAL: gamma0, gamma1, gamma2), their errors, chi2, dof
+    and the fitted points (x, y, err)."""
+    N = np.ascontiguousarray(np.asarray(N, dtype=np.float64))
+    ts = np.ascontiguousarray(np.asarray(tstar, dtype=np.float64))
+    if ts.size != N.size:
+        raise ValueError("N and tstar differ in length")
+    e = None if tstar_err is None else np.ascontiguousarray(np.asarray(tstar_err, dtype=np.float64))
+    if e is not None and e.size != N.size:
+        raise ValueError("N and tstar_err differ in length")
+    cap = max(N.size * N.size, 1)
+    px, py, pe = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    o = FitOpts(int(method), int(terms), int(dN))
+    r = FitResult()
+    dp = lambda a: None if a is None else a.ctypes.data_as(_dp)
+    _check(_lib.syk_lyapunov_fit(dp(N), dp(ts), dp(e), N.size, ct.byref(o), ct.byref(r), dp(px), dp(py), dp(pe), cap))
+    out = {"lambda": r.lambda_, "lambda_err": r.lambda_err, "chi2": r.chi2, "n_points": r.n_points, "dof": r.dof}
+    names = ("alpha1", "alpha2", None) if method == FIT_SLOPE else ("gamma0", "gamma1", "gamma2")
+    for c, nm in enumerate(names):
+        if nm:
+            out[nm], out[nm + "_err"] = r.coef[c], r.coef_err[c]
+    n = r.n_points
+    out["points"] = (px[:n].copy(), py[:n].copy(), pe[:n].copy())
+    return out
 
 
 def workspace_bytes(N: int, m: int, dtype: int, nvec: int = 1) -> int:

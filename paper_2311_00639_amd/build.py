@@ -12,7 +12,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsyk.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["terms.cpp", "runtime.cpp", "apply_plan.cpp", "krylov.cpp", "otoc.cpp", "engine.cpp", "batch.cpp", "op.cpp", "api.cpp"]
+HOST_SOURCES = ["terms.cpp", "runtime.cpp", "apply_plan.cpp", "krylov.cpp", "otoc.cpp", "engine.cpp", "batch.cpp", "op.cpp", "analysis.cpp", "otoc_ensemble.cpp", "api.cpp"]
 HIP_SOURCES = ["kernels.hip", "apply_tiled.hip", "batch.hip"]
 
 HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-Wextra", "-Wno-unused-parameter",

@@ -3,14 +3,18 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <limits>
 #include <string>
+#include <vector>
 
+#include "analysis.hpp"
 #include "apply_plan.hpp"
 #include "batch.hpp"
 #include "engine.hpp"
 #include "krylov.hpp"
 #include "op.hpp"
 #include "otoc.hpp"
+#include "otoc_ensemble.hpp"
 
 struct syk_ham {
     syk::Hamiltonian h;
@@ -412,9 +416,15 @@ syk_status syk_otoc_batch(const syk_batch_item *items, int n_items, const double
             check_N(it.N);
             require(it.N / 2 - 1 >= 8 && it.N / 2 - 1 <= 15, "batched items need 18 <= N <= 32");
             require(std::isfinite(it.k) && it.k > 0.0, "k must be positive");
-            const double K = std::floor(it.k * it.N + 0.5);
-            require(K >= 1.0 && K <= it.N * (it.N - 1.0) * (it.N - 2.0) * (it.N - 3.0) / 24.0,
-                    "K = round(k N) must lie in [1, C(N,4)]");
+            require(it.ensemble == SYK_ENSEMBLE_EXACT_K || it.ensemble == SYK_ENSEMBLE_BERNOULLI,
+                    "unknown ensemble");
+            const double C4 = it.N * (it.N - 1.0) * (it.N - 2.0) * (it.N - 3.0) / 24.0;
+            if (it.ensemble == SYK_ENSEMBLE_EXACT_K) {
+                const double K = std::floor(it.k * it.N + 0.5);
+                require(K >= 1.0 && K <= C4, "K = round(k N) must lie in [1, C(N,4)]");
+            } else {
+                require(it.k * it.N <= C4, "Bernoulli ensemble needs p = k N / C(N,4) <= 1");
+            }
             require(it.i >= 0 && it.i < it.N && it.j >= 0 && it.j < it.N && it.i != it.j,
                     "Majorana indices must be distinct and in [0, N)");
         }
@@ -422,6 +432,151 @@ syk_status syk_otoc_batch(const syk_batch_item *items, int n_items, const double
         syk_batch_stats st{};
         syk::otoc_batch(items, n_items, t, nt, *o, F_raw, F_norm, F_imag, st, as_stream(stream));
         if (stats) *stats = st;
+    });
+}
+
+syk_status syk_otoc_ensemble(const syk_ensemble_desc *d, const double *t, int nt, const syk_otoc_opts *o,
+                             double *F_mean, double *F_sem, double *F_rows, syk_ensemble_stats *stats,
+                             void *stream) {
+    return guarded([&] {
+        require(d && t && o, "NULL argument");
+        check_N(d->N);
+        require(std::isfinite(d->k) && d->k > 0.0, "k must be positive");
+        require(d->ensemble == SYK_ENSEMBLE_EXACT_K || d->ensemble == SYK_ENSEMBLE_BERNOULLI, "unknown ensemble");
+        require(d->n_real >= 1, "n_real must be >= 1");
+        require(d->path >= -1 && d->path <= 1, "path must be -1, 0 or 1");
+        syk::check_otoc_args(d->N, d->i, d->j, d->beta, t, nt, *o);
+        if (d->path == 0 && !syk::ensemble_batch_eligible(*d, *o))
+            syk::fail(SYK_EUNSUPPORTED, "the batched path needs complex64, 18 <= N <= 32, m <= 60 and no profiling");
+        check_device();
+        syk_ensemble_stats st{};
+        syk::otoc_ensemble(*d, t, nt, *o, F_mean, F_sem, F_rows, st, as_stream(stream));
+        if (stats) *stats = st;
+    });
+}
+
+syk_status syk_crossing_time(const double *t, const double *F, const double *F_err, int nt, double F0,
+                             double *tstar, double *tstar_err) {
+    return guarded([&] {
+        require(t && F && tstar, "NULL argument");
+        require(nt >= 2, "nt must be >= 2");
+        require(std::isfinite(F0), "F0 must be finite");
+        for (int k = 0; k < nt; ++k) {
+            require(std::isfinite(t[k]) && std::isfinite(F[k]), "t and F must be finite");
+            if (F_err) require(std::isfinite(F_err[k]) && F_err[k] >= 0.0, "F_err must be finite and >= 0");
+            if (k) require(t[k] >= t[k - 1], "t must be non-decreasing");
+        }
+        syk::crossing_time(t, F, F_err, nt, F0, *tstar, tstar_err);
+    });
+}
+
+syk_status syk_lyapunov_fit(const double *N, const double *tstar, const double *tstar_err, int n,
+                            const syk_fit_opts *o, syk_fit_result *out, double *pts_N, double *pts_y,
+                            double *pts_err, int cap) {
+    return guarded([&] {
+        require(N && tstar && o && out, "NULL argument");
+        require(n >= 1, "n must be >= 1");
+        require(o->method == SYK_FIT_SLOPE || o->method == SYK_FIT_GLOBAL, "unknown fit method");
+        require(o->terms >= 0 && o->terms <= 3, "terms must be a mask of bits 0 and 1");
+        for (int a = 0; a < n; ++a) {
+            require(std::isfinite(N[a]) && N[a] > 1.0, "N must be finite and > 1");
+            require(std::isfinite(tstar[a]), "t* must be finite");
+            if (tstar_err) require(std::isfinite(tstar_err[a]) && tstar_err[a] > 0.0, "t* errors must be positive");
+        }
+        const double nan = std::numeric_limits<double>::quiet_NaN();
+        // points (x = N or N_mid, value, sigma)
+        std::vector<double> px, py, pe;
+        if (o->method == SYK_FIT_SLOPE) {
+            require(o->dN >= 1, "dN must be >= 1");
+            for (const auto &sp : syk::slope_points(N, tstar, tstar_err, n, o->dN)) {
+                px.push_back(sp.N_mid);
+                py.push_back(sp.y);
+                pe.push_back(sp.err);
+            }
+        } else {
+            for (int a = 0; a < n; ++a) {
+                px.push_back(N[a]);
+                py.push_back(tstar[a]);
+                pe.push_back(tstar_err ? tstar_err[a] : nan);
+            }
+        }
+        const int np = static_cast<int>(px.size());
+        require(np >= 1, "no pair (N, N + dN) in the data");
+        const bool t1 = o->terms & 1, t2 = o->terms & 2;
+        // columns: SLOPE 1, 1/N, 1/N^2; GLOBAL 1, log N, log N/N, log N/N^2
+        std::vector<double> A;
+        int k = 0;
+        for (int a = 0; a < np; ++a) {
+            const double x = px[a];
+            std::vector<double> row;
+            if (o->method == SYK_FIT_SLOPE) {
+                row.push_back(1.0);
+                if (t1) row.push_back(1.0 / x);
+                if (t2) row.push_back(1.0 / (x * x));
+            } else {
+                const double lg = std::log(x);
+                row.push_back(1.0);
+                row.push_back(lg);
+                if (t1) row.push_back(lg / x);
+                if (t2) row.push_back(lg / (x * x));
+            }
+            k = static_cast<int>(row.size());
+            A.insert(A.end(), row.begin(), row.end());
+        }
+        std::vector<double> w(np, 1.0);
+        if (tstar_err)
+            for (int a = 0; a < np; ++a) {
+                require(std::isfinite(pe[a]) && pe[a] > 0.0, "fit point error must be positive");
+                w[a] = 1.0 / (pe[a] * pe[a]);
+            }
+        const syk::LsqSolution sol = syk::least_squares(A, py, w, np, k);
+        std::vector<double> cov = sol.cov;
+        const int dof = np - k;
+        if (!tstar_err)
+            for (double &c : cov) c = dof > 0 ? c * sol.rss / dof : nan;
+        syk_fit_result r{};
+        r.chi2 = sol.rss;
+        r.n_points = np;
+        r.dof = dof;
+        if (o->method == SYK_FIT_SLOPE) {
+            r.lambda = sol.p[0];
+            r.lambda_err = std::sqrt(cov[0]);
+            int c = 1;
+            if (t1) { r.coef[0] = sol.p[c]; r.coef_err[0] = std::sqrt(cov[c * k + c]); ++c; }
+            if (t2) { r.coef[1] = sol.p[c]; r.coef_err[1] = std::sqrt(cov[c * k + c]); }
+        } else {
+            // q = (gamma_0, a, b, c): lambda = 1/a, gamma_1 = b/a, gamma_2 = c/a; J dq -> dparams
+            const double a = sol.p[1];
+            std::vector<double> J(static_cast<size_t>(k) * k, 0.0);
+            J[0] = 1.0;
+            J[1 * k + 1] = -1.0 / (a * a);
+            for (int c = 2; c < k; ++c) {
+                J[c * k + 1] = -sol.p[c] / (a * a);
+                J[c * k + c] = 1.0 / a;
+            }
+            auto var = [&](int row) {
+                double s = 0.0;
+                for (int x = 0; x < k; ++x)
+                    for (int y = 0; y < k; ++y) s += J[row * k + x] * cov[x * k + y] * J[row * k + y];
+                return std::sqrt(s);
+            };
+            r.lambda = 1.0 / a;
+            r.lambda_err = var(1);
+            r.coef[0] = sol.p[0];
+            r.coef_err[0] = var(0);
+            int c = 2;
+            if (t1) { r.coef[1] = sol.p[c] / a; r.coef_err[1] = var(c); ++c; }
+            if (t2) { r.coef[2] = sol.p[c] / a; r.coef_err[2] = var(c); }
+        }
+        if (pts_N || pts_y || pts_err) {
+            require(cap >= np, "cap is below the number of fitted points");
+            for (int a = 0; a < np; ++a) {
+                if (pts_N) pts_N[a] = px[a];
+                if (pts_y) pts_y[a] = py[a];
+                if (pts_err) pts_err[a] = pe[a];
+            }
+        }
+        *out = r;
     });
 }
 

@@ -95,7 +95,7 @@ void otoc_batch(const syk_batch_item *items, int n_items, const double *t, int n
     for (int r = 0; r < n_items; ++r) {
         const syk_batch_item &it = items[r];
         Hamiltonian h;
-        build_hamiltonian(h, it.N, it.k, it.seed);
+        build_hamiltonian(h, it.N, it.k, it.seed, it.ensemble);
         BatchJob jb{};
         jb.L = h.L;
         jb.N = h.N;

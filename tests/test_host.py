@@ -10,7 +10,7 @@ import pytest
 import scipy.linalg
 
 import paper_2311_00639_amd as syk
-from oracle import ensemble, pauli
+from oracle import ensemble, lyapunov, pauli
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -225,3 +225,98 @@ def test_operator_argument_errors():
         syk.Operator(3, [1], [0], [float("nan")])
     with pytest.raises(syk.SykError):
         syk.Operator(3, [1], [0], [1.0]) @ syk.Operator(4, [1], [0], [1.0])
+
+
+# ---------------------------------------------------------------- t*(N) and lambda_L (host code)
+
+def test_crossing_time_matches_oracle():
+    rng = np.random.default_rng(11)
+    for trial in range(30):
+        nt = int(rng.integers(2, 40))
+        t = np.cumsum(rng.uniform(0.0, 0.3, nt))
+        F = 1.0 - np.cumsum(rng.uniform(-0.02, 0.08, nt))
+        err = rng.uniform(0.0, 0.01, nt)
+        F0 = float(rng.uniform(0.5, 1.0))
+        a = syk.crossing_time(t, F, F0, err)
+        b = lyapunov.crossing_time(t, F, F0, err)
+        if math.isnan(b[0]):
+            assert math.isnan(a[0]) and math.isnan(a[1])
+        else:
+            assert a[0] == pytest.approx(b[0], rel=1e-14, abs=1e-14)
+            assert a[1] == pytest.approx(b[1], rel=1e-12, abs=1e-15)
+    ts, e = syk.crossing_time([0.0, 1.0, 2.0], [1.0, 0.9, 0.7], 0.8)
+    assert ts == pytest.approx(1.5) and math.isnan(e)
+
+
+@pytest.mark.parametrize("terms", [0, 1, 2, 3])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_lyapunov_fits_match_oracle(terms, weighted):
+    rng = np.random.default_rng(terms + 5 * weighted)
+    N = np.array([54.0, 14.0, 30.0, 22.0, 46.0, 38.0, 62.0])     # unsorted on purpose
+    sig = rng.uniform(0.02, 0.06, N.size)
+    ts = -0.4 + np.log(N) / 0.65 * (1 + 1.5 / N) + sig * rng.standard_normal(N.size)
+    e = sig if weighted else None
+    a = syk.lyapunov_fit(N, ts, e, method=syk.FIT_SLOPE, terms=terms)
+    Nm, y, ye = lyapunov.slope_points(N, ts, e)
+    b = lyapunov.fit_slope(Nm, y, ye if weighted else None, a1=bool(terms & 1), a2=bool(terms & 2))
+    for key in ("lambda", "lambda_err", "alpha1", "alpha1_err", "alpha2", "alpha2_err", "chi2"):
+        assert a[key] == pytest.approx(b[key], rel=1e-9, abs=1e-12), key
+    assert a["dof"] == b["dof"] and a["n_points"] == len(y) == 6
+    order = np.argsort(a["points"][0])
+    assert np.allclose(a["points"][0][order], np.sort(Nm)) and np.allclose(a["points"][1][order], y[np.argsort(Nm)])
+    a = syk.lyapunov_fit(N, ts, e, method=syk.FIT_GLOBAL, terms=terms)
+    b = lyapunov.fit_global(N, ts, e, g1=bool(terms & 1), g2=bool(terms & 2))
+    for key in ("lambda", "lambda_err", "gamma0", "gamma0_err", "gamma1", "gamma1_err", "gamma2", "gamma2_err",
+                "chi2"):
+        assert a[key] == pytest.approx(b[key], rel=1e-8, abs=1e-12), key
+    assert a["dof"] == b["dof"] == N.size - 2 - bin(terms).count("1")
+
+
+def test_lyapunov_fit_recovers_scaling_form_exactly():
+    lam = 0.81
+    N = np.array([22.0, 30.0, 38.0, 46.0, 54.0])
+    r = syk.lyapunov_fit(N, 0.3 + np.log(N) / lam, method=syk.FIT_SLOPE, terms=0)
+    assert r["lambda"] == pytest.approx(lam, rel=1e-13) and r["lambda_err"] == pytest.approx(0.0, abs=1e-12)
+    r = syk.lyapunov_fit(N, 0.3 + np.log(N) / lam * (1 - 2.0 / N), method=syk.FIT_GLOBAL, terms=1)
+    assert r["lambda"] == pytest.approx(lam, rel=1e-11) and r["gamma1"] == pytest.approx(-2.0, abs=1e-8)
+    assert r["gamma0"] == pytest.approx(0.3, abs=1e-9)
+
+
+def test_lyapunov_fit_errors():
+    N = np.array([14.0, 22.0, 30.0])
+    ts = np.array([1.0, 1.5, 1.8])
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit(N, ts, method=syk.FIT_SLOPE, terms=3)               # 2 pairs, 3 parameters
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit([14.0, 30.0], [1.0, 2.0], method=syk.FIT_SLOPE)      # no pair 8 apart
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit(N, [1.0, 1.0, 1.8], method=syk.FIT_SLOPE)            # equal t* in a pair
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit(N, [1.0, np.nan, 1.8], method=syk.FIT_GLOBAL)
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit(N, ts, [0.1, 0.0, 0.1], method=syk.FIT_GLOBAL)        # zero error
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit(N, ts, method=5)
+    with pytest.raises(syk.SykError):
+        syk.lyapunov_fit([30.0, 30.0, 30.0], ts, method=syk.FIT_GLOBAL, terms=0)   # dependent columns
+    r = syk.lyapunov_fit(N, ts, method=syk.FIT_GLOBAL, terms=1)                # dof = 0: no errors
+    assert r["dof"] == 0 and math.isnan(r["lambda_err"])
+    with pytest.raises(syk.SykError):
+        syk.crossing_time([0.0, 1.0], [1.0, 0.5], math.inf)
+    with pytest.raises(syk.SykError):
+        syk.crossing_time([1.0, 0.0], [1.0, 0.5], 0.8)
+    with pytest.raises(syk.SykError):
+        syk.crossing_time([0.0], [1.0], 0.8)
+
+
+def test_otoc_ensemble_argument_checks_without_gpu():
+    ts = [0.0, 1.0]
+    with pytest.raises(syk.SykError):
+        syk.otoc_ensemble(24, 4, 1, 0, 23, 22, 1.0, ts)            # n_real < 1
+    with pytest.raises(syk.SykError):
+        syk.otoc_ensemble(24, 4, 1, 2, 23, 23, 1.0, ts)            # i == j
+    with pytest.raises(syk.SykError) as e:
+        syk.otoc_ensemble(40, 4, 1, 2, 39, 38, 1.0, ts, path=0)    # batched path cannot serve N = 40
+    assert e.value.status == 2
+    with pytest.raises(syk.SykError):
+        syk.otoc_ensemble(24, 4, 1, 2, 23, 22, 1.0, ts, ensemble=7)
