@@ -3,7 +3,8 @@
 Workload (mixed precision at scale): N = 56 Majoranas (parity blocks of 2^27 amplitudes),
 q = 4, k = 4 (K = 224 terms), one disorder realisation (seed 56), complex64 state
 vectors with double Lanczos reductions and tridiagonal exponential, Krylov dimension 60,
-one Haar state (state_seed 5600), W = chi_55, V = chi_54, beta in {5, 10, 20},
+per-propagation tolerance 1e-6 (complex64 rounding, not the tolerance, sets the error of F;
+the mixed_precision leg reports it), one Haar state (state_seed 5600), W = chi_55, V = chi_54, beta in {5, 10, 20},
 t = 0, 0.25, ..., 20 (81 points).
 
 A step is one complete OTOC curve (one beta, both parity-block chains, all 81 t points);
@@ -44,6 +45,7 @@ sys.path.insert(0, ROOT)
 N, K_SPARSITY, SEED, STATE_SEED = 56, 4, 56, 5600
 BETAS = (10.0, 5.0, 20.0)
 M_KRYLOV = 60
+TOL_C64 = 1e-6
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
@@ -204,7 +206,7 @@ def main():
 
     if args.pmc_sample:
         raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, BETAS[0], [0.0, 0.25, 0.5], state_seed=STATE_SEED,
-                                    dtype=syk.C64, m=M_KRYLOV, profile=True, stream=stream)
+                                    dtype=syk.C64, m=M_KRYLOV, tol=TOL_C64, profile=True, stream=stream)
         x = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
         x.zero_()
         y = x.clone()                     # calibration: 1 GiB read, 1 GiB written
@@ -225,7 +227,7 @@ def main():
                 print(f"[bench] beta={beta:g}: {done}/{total} chain t-points, {time.perf_counter() - t_start:.0f} s",
                       file=sys.stderr, flush=True)
         return syk.otoc(h, N - 1, N - 2, beta, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64, m=M_KRYLOV,
-                        profile=profile, progress=progress, stream=stream)
+                        tol=TOL_C64, profile=profile, progress=progress, stream=stream)
 
     for w in range(args.warmup):
         curve(BETAS[w % 3], False)
@@ -270,9 +272,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "sparse SYK OTOC realisation: N=56, q=4, k=4 (K=224), complex64 states, "
-                               "double Lanczos reductions, Krylov dim 60, beta in {5,10,20}, t=0:0.25:20, "
+                               "double Lanczos reductions, Krylov dim 60, tol 1e-6, beta in {5,10,20}, t=0:0.25:20, "
                                "1 Haar state, W=chi_55, V=chi_54; one step = one beta curve",
-                   "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "betas": list(BETAS), "nt": len(ts),
+                   "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "krylov_tol": TOL_C64, "betas": list(BETAS), "nt": len(ts),
                    "betas_timed": [b for b, _ in results], "parallelism": "single GPU"},
         "apply_H_term_amps_per_s": term_amps / avg_s,
         "apply_H_ms": avg_s * 1e3,

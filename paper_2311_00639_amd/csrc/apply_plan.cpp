@@ -16,6 +16,7 @@
 //    taken.
 #include <algorithm>
 #include <array>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <tuple>
@@ -269,6 +270,8 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
     std::map<uint32_t, std::vector<int>> byg;
     for (int a = 0; a < static_cast<int>(terms.size()); ++a) byg[rotr_bits(terms[a].x, s, L) >> bt].push_back(a);
     std::unordered_map<uint32_t, std::array<uint32_t, 3>> range;   // g -> (first, mid, end)
+    std::vector<std::array<uint32_t, 5>> compact;                   // sr = 2: per-term block record
+    const uint32_t rec_dw = block_record_dwords(elem_bytes), rec_max = block_records(elem_bytes);
     uint32_t count = 0;
     for (const auto &kv : byg) {
         std::array<uint32_t, 3> r{count, 0u, 0u};
@@ -284,7 +287,22 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
                 hp.meta.push_back(xl & tmask);
                 hp.meta.push_back(z & tmask);
                 hp.meta.push_back(z >> bt);
-                if (sr) {
+                if (sr == 2) {
+                    // (thread bits of x | xr << 24, thread bits of z | register sign mask << 24,
+                    //  z >> bt, coefficient as float or as the two dwords of a double): bit q of the
+                    //  sign mask is the parity of q & zr
+                    uint32_t smask = 0;
+                    for (uint32_t q = 0; q <= rmask; ++q) smask |= (__builtin_popcount(q & zr) & 1u) << q;
+                    std::array<uint32_t, 5> rec{(xl & tmask) | (xr << 24), (z & tmask) | (smask << 24), z >> bt, 0u, 0u};
+                    if (elem_bytes == 8) {
+                        const float cf = static_cast<float>(t.c);
+                        std::memcpy(&rec[3], &cf, 4);
+                    } else {
+                        std::memcpy(&rec[3], &t.c, 8);
+                    }
+                    compact.push_back(rec);
+                    hp.meta.resize(hp.meta.size() - 3);
+                } else if (sr) {
                     hp.meta.push_back((xr << rb) | zr);        // code of the compiled register path
                 } else {
                     hp.meta.push_back(0u);
@@ -300,7 +318,7 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
         r[2] = count;
         range[kv.first] = r;
     }
-    hp.meta.resize(hp.meta.size() + (sr ? 4 : 4 + 2 * (rmask + 1)), 0u);   // one padding record (prefetch)
+    if (sr != 2) hp.meta.resize(hp.meta.size() + (sr ? 4 : 4 + 2 * (rmask + 1)), 0u);   // padding record (prefetch)
     hp.c.push_back(0.0);
 
     // partner schedule: class by class modulo Wg, then Wx (both with span(H)), then offset
@@ -320,11 +338,37 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
     const size_t tpw = hp.hvec.size();
     for (const auto &o : order) {
         const uint32_t p = std::get<2>(o);
-        hp.pi.push_back(p);
+        std::vector<std::array<uint32_t, 3>> rs(tpw);
+        uint32_t total = 0;
         for (size_t i = 0; i < tpw; ++i) {
             auto it = range.find(p ^ hp.hvec[i]);
-            const std::array<uint32_t, 3> r = it == range.end() ? std::array<uint32_t, 3>{0u, 0u, 0u} : it->second;
-            hp.ranges.insert(hp.ranges.end(), r.begin(), r.end());
+            rs[i] = it == range.end() ? std::array<uint32_t, 3>{0u, 0u, 0u} : it->second;
+            total += rs[i][2] - rs[i][0];
+        }
+        if (sr != 2 || total <= rec_max) {
+            hp.pi.push_back(p);
+            for (size_t i = 0; i < tpw; ++i) hp.ranges.insert(hp.ranges.end(), rs[i].begin(), rs[i].end());
+            continue;
+        }
+        // control blocks hold at most rec_max records: split the step, repeating the
+        // partner, each part taking the next records in (tile, real, imaginary) order
+        std::vector<std::pair<size_t, uint32_t>> flat;
+        for (size_t q = 0; q < tpw; ++q)
+            for (uint32_t t = rs[q][0]; t < rs[q][2]; ++t) flat.emplace_back(q, t);
+        for (size_t c0 = 0; c0 < flat.size(); c0 += rec_max) {
+            const size_t c1 = std::min<size_t>(flat.size(), c0 + rec_max);
+            hp.pi.push_back(p);
+            for (size_t q = 0; q < tpw; ++q) {
+                uint32_t lo = 0, hi = 0;
+                bool any = false;
+                for (size_t e = c0; e < c1; ++e)
+                    if (flat[e].first == q) {
+                        if (!any) lo = flat[e].second;
+                        hi = flat[e].second + 1;
+                        any = true;
+                    }
+                hp.ranges.insert(hp.ranges.end(), {lo, any ? std::min(std::max(rs[q][1], lo), hi) : 0u, hi});
+            }
         }
     }
     const uint32_t last = hp.pi.empty() ? 0u : hp.pi.back();
@@ -334,6 +378,28 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
     }
     hp.n_pi = static_cast<int>(hp.pi.size());
     for (int k = 0; k < extra; ++k) hp.pi.push_back(last);                      // targets of the last prefetches
+    if (sr == 2) {
+        // one 64-dword control block per partner step (and one more for the last prefetch):
+        // lanes rec_dw j .. rec_dw (j + 1) - 1 record j, lane 60 the record counts (tile i: real in bits 8i..8i+3,
+        // imaginary in 8i+4..8i+7), lane 61 the partner offset copied during that step
+        hp.meta.assign(static_cast<size_t>(hp.n_pi + 1) * 64, 0u);
+        for (int st = 0; st <= hp.n_pi; ++st) {
+            uint32_t *blk = &hp.meta[static_cast<size_t>(st) * 64];
+            blk[61] = hp.pi[std::min<size_t>(st + extra, hp.pi.size() - 1)];
+            if (st == hp.n_pi) continue;
+            uint32_t j = 0, counts = 0;
+            for (size_t i = 0; i < tpw; ++i) {
+                const uint32_t *r = &hp.ranges[(static_cast<size_t>(st) * tpw + i) * 3];
+                if (r[1] - r[0] > 15 || r[2] - r[1] > 15) fail(SYK_EDEVICE, "control block count overflow");
+                counts |= ((r[1] - r[0]) << (8 * i)) | ((r[2] - r[1]) << (8 * i + 4));
+                for (uint32_t a = r[0]; a < r[2]; ++a, ++j) {
+                    if (j >= rec_max) fail(SYK_EDEVICE, "control block record overflow");
+                    for (uint32_t f = 0; f < rec_dw; ++f) blk[rec_dw * j + f] = compact[a][f];
+                }
+            }
+            blk[60] = counts;
+        }
+    }
     return hp;
 }
 

@@ -12,6 +12,11 @@ namespace syk {
 // tiles t0 ^ hvec[i]; for each partner offset pi (partner tile t0 ^ pi) it applies the
 // term group g = pi ^ hvec[i] to tile i, whose records are [first, mid) (real phase) and
 // [mid, end) (i phase) at ranges[(step * 2^w + i) * 3].
+// record form 2: dwords per record (4 + one more for a double coefficient) and records per
+// 64-dword control block (lanes 0..59 hold records, 60 and 61 the counts and next partner)
+inline uint32_t block_record_dwords(uint32_t elem_bytes) { return elem_bytes == 8 ? 4u : 5u; }
+inline uint32_t block_records(uint32_t elem_bytes) { return 60u / block_record_dwords(elem_bytes); }
+
 struct HostPlan {
     int rot = 0, w = 0;
     uint32_t n_tiles = 0, n_wg = 0;

@@ -145,12 +145,62 @@ __device__ __forceinline__ void apply_terms_static(typename V2t<T>::type (&acc)[
     }
 }
 
+// Control-block records (record form 2): a wave holds the current partner step's 64-dword
+// control block in one VGPR (lane l = dword l) and reads a record's four dwords with
+// readlane into scalar registers, so the term loop issues no scalar memory load (those
+// share the LDS reads' counter and would make every LDS wait also wait for them).
+// Record: (thread bits of x | xr << 24, thread bits of z | sign mask << 24, z >> BT,
+// coefficient: one dword for float, two for double); bit r of the sign mask is the
+// parity of r & zr.
+template <typename T, int BT, int RB, bool IM>
+__device__ __forceinline__ void block_term(typename V2t<T>::type (&acc)[1 << RB], const typename V2t<T>::type *b,
+                                           uint32_t cur, int j, uint32_t tile, uint32_t tid) {
+    using V = typename V2t<T>::type;
+    constexpr int R = 1 << RB;
+    constexpr int TB = BT - RB;
+    constexpr int SH = TB + (sizeof(T) == 4 ? 3 : 4);   // byte shift of the register index
+    constexpr int RD = sizeof(T) == 4 ? 4 : 5;          // dwords per record
+    const uint32_t w0 = __builtin_amdgcn_readlane(cur, RD * j);
+    const uint32_t w1 = __builtin_amdgcn_readlane(cur, RD * j + 1);
+    const uint32_t w2 = __builtin_amdgcn_readlane(cur, RD * j + 2);
+    const uint32_t w3 = __builtin_amdgcn_readlane(cur, RD * j + 3);
+    T c;
+    if constexpr (sizeof(T) == 4) {
+        c = __uint_as_float(w3);
+    } else {
+        const uint32_t w4 = __builtin_amdgcn_readlane(cur, RD * j + 4);
+        c = __hiloint2double(static_cast<int>(w4), static_cast<int>(w3));
+    }
+    const uint32_t xt = w0 & 0xffffffu, xr = w0 >> 24;
+    const uint32_t zt = w1 & 0xffffffu, sm = w1 >> 24;
+    const uint32_t par = (__popc(tile & w2) + __popc(tid & zt)) & 1u;
+    const T cl = flip_sign(c, par << 31);
+    const uint32_t base = ((tid ^ xt) << (SH - TB)) | (xr << SH);
+    const char *bb = reinterpret_cast<const char *>(b);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const V q = *reinterpret_cast<const V *>(bb + (base ^ (static_cast<uint32_t>(r) << SH)));
+        // the register sign stays a scalar operand: one vector XOR per register (output
+        // register 0 never changes sign: r & zr = 0)
+        uint32_t sg = ((sm >> r) & 1u) << 31;
+        asm("" : "+s"(sg));
+        const T cr = r == 0 ? cl : flip_sign(cl, sg);
+        if (IM) {
+            acc[r].x -= cr * q.y;
+            acc[r].y += cr * q.x;
+        } else {
+            acc[r].x += cr * q.x;
+            acc[r].y += cr * q.y;
+        }
+    }
+}
+
 // one group's terms (real-phase terms [t0, tm), i-phase terms [tm, t1)) in either record form
 template <typename T, int BT, int RB, int SR>
 __device__ __forceinline__ void group_terms(typename V2t<T>::type (&acc)[1 << RB], const typename V2t<T>::type *b,
                                             const void *recs, const T *__restrict__ coef, int t0, int tm, int t1,
                                             uint32_t tile, uint32_t tid) {
-    if constexpr (SR) {
+    if constexpr (SR == 1) {
         const TermRec4 *r = static_cast<const TermRec4 *>(recs);
         apply_terms_static<T, BT, RB, false>(acc, b, r, coef, t0, tm, tile, tid);
         apply_terms_static<T, BT, RB, true>(acc, b, r, coef, tm, t1, tile, tid);
@@ -259,7 +309,48 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
         static_for<0, TPW>(one);
     };
 
-    if constexpr (NBUF == 1) {
+    if constexpr (SR == 2) {
+        // two buffers; the control block of step k + 1 is loaded during step k, just before
+        // the copy of the partner of step k + 1, so the wait for that copy covers it too
+        static_assert(NBUF == 2 && RB <= 3, "control blocks: 2 buffers, at most 8 registers per thread");
+        const uint32_t *blocks = static_cast<const uint32_t *>(recs);
+        const uint32_t lane = tid & 63u;
+        dma_tile<T, BT, RB>(partner(0), b0, tid);
+        uint32_t blk0 = blocks[lane], blk1 = 0;
+        auto terms_blk = [&](const V *b, uint32_t cur) __attribute__((always_inline)) {
+            const uint32_t cnt = __builtin_amdgcn_readlane(cur, 60);
+            int j = 0;
+            static_for<0, TPW>([&](auto ic) __attribute__((always_inline)) {
+                constexpr int i = decltype(ic)::value;
+                const uint32_t tile = t0 ^ hs.h[i];
+                const int nre = static_cast<int>((cnt >> (8 * i)) & 15u);
+                const int nim = static_cast<int>((cnt >> (8 * i + 4)) & 15u);
+                for (const int e = j + nre; j < e; ++j) block_term<T, BT, RB, false>(acc[i], b, cur, j, tile, tid);
+                for (const int e = j + nim; j < e; ++j) block_term<T, BT, RB, true>(acc[i], b, cur, j, tile, tid);
+            });
+        };
+        for (int k0 = 0; k0 < n_pi; k0 += 2) {
+            auto step = [&](auto kc) __attribute__((always_inline)) {
+                constexpr int K = decltype(kc)::value;
+                const int k = k0 + K;
+                __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_barrier();
+                asm volatile("" ::: "memory");
+                const uint32_t cur = K == 0 ? blk0 : blk1;
+                const uint32_t nxt = blocks[static_cast<size_t>(k + 1) * 64 + lane];
+                if constexpr (K == 0)
+                    blk1 = nxt;
+                else
+                    blk0 = nxt;
+                const uint32_t pn = __builtin_amdgcn_readlane(cur, 61);
+                dma_tile<T, BT, RB>(xv + (static_cast<uint64_t>(t0 ^ pn) << BT), K == 0 ? b1 : b0, tid);
+                terms_blk(K == 0 ? b0 : b1, cur);
+            };
+            step(std::integral_constant<int, 0>{});
+            step(std::integral_constant<int, 1>{});
+        }
+    } else if constexpr (NBUF == 1) {
         for (int k = 0; k < n_pi; ++k) {
             // the previous step's reads of b0 ended at the barrier closing it
             dma_tile<T, BT, RB>(partner(k), b0, tid);
@@ -412,6 +503,9 @@ void launch_apply_tiled(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_
         SYK_TV(13, 3, 2, 1, 0, 1)
         SYK_TV(13, 3, 2, 1, 0, 2)
         SYK_TV(12, 3, 2, 2, 0, 1)
+        SYK_TV(13, 3, 2, 1, 2, 0)
+        SYK_TV(13, 3, 2, 1, 2, 1)
+        SYK_TV(13, 3, 2, 1, 2, 2)
     } else {
         SYK_TV(12, 2, 2, 1, 0, 0)
         SYK_TV(12, 2, 1, 2, 0, 0)
@@ -421,6 +515,9 @@ void launch_apply_tiled(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_
         SYK_TV(12, 2, 2, 1, 0, 1)
         SYK_TV(12, 2, 2, 1, 0, 2)
         SYK_TV(11, 2, 2, 2, 0, 1)
+        SYK_TV(12, 2, 2, 1, 2, 0)
+        SYK_TV(12, 2, 2, 1, 2, 1)
+        SYK_TV(12, 2, 2, 1, 2, 2)
     }
 #undef SYK_TV
     fail(SYK_EDEVICE, "unknown tiled apply_H variant");

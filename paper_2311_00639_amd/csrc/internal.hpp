@@ -53,7 +53,9 @@ struct DeviceTables {            // per device, per block: real terms first, the
 // pf extra partner entries at the end of the group list, occ workgroups resident per CU
 // (the planner's XCD-resident subspace has dimension 5 + log2(occ)); sr = 1: each term's
 // register permutation and register signs select a compiled code path (4-dword term
-// records), sr = 0: they are read from the term record (4 + 2 * 2^rb dwords); each
+// records), sr = 0: they are read from the term record (4 + 2 * 2^rb dwords), sr = 2: each
+// partner step's records sit in a 64-dword control block that a wave holds in one VGPR
+// and reads with readlane (no scalar memory loads in the term loop; two buffers); each
 // workgroup keeps 2^w output tiles in registers and streams the union of their partner
 // tiles once.
 struct TiledVariant {

@@ -67,23 +67,26 @@ template <>
 const std::vector<TiledVariant> &tiled_variants<float>() {
     static const std::vector<TiledVariant> v = {{13, 3, 2, 1, 1, 0, 0}, {13, 3, 1, 0, 2, 0, 0}, {12, 3, 2, 1, 2, 0, 0},
                                                 {12, 2, 4, 3, 1, 0, 0}, {13, 3, 2, 1, 1, 1, 0}, {13, 3, 2, 1, 1, 0, 1},
-                                                {13, 3, 2, 1, 1, 0, 2}, {12, 3, 2, 1, 2, 0, 1}};
+                                                {13, 3, 2, 1, 1, 0, 2}, {12, 3, 2, 1, 2, 0, 1}, {13, 3, 2, 1, 1, 2, 0},
+                                                {13, 3, 2, 1, 1, 2, 1}, {13, 3, 2, 1, 1, 2, 2}};
     return v;
 }
 template <>
 const std::vector<TiledVariant> &tiled_variants<double>() {
     static const std::vector<TiledVariant> v = {{12, 2, 2, 1, 1, 0, 0}, {12, 2, 1, 0, 2, 0, 0}, {11, 2, 2, 1, 2, 0, 0},
                                                 {11, 1, 4, 3, 1, 0, 0}, {12, 2, 2, 1, 1, 1, 0}, {12, 2, 2, 1, 1, 0, 1},
-                                                {12, 2, 2, 1, 1, 0, 2}, {11, 2, 2, 1, 2, 0, 1}};
+                                                {12, 2, 2, 1, 1, 0, 2}, {11, 2, 2, 1, 2, 0, 1}, {12, 2, 2, 1, 1, 2, 0},
+                                                {12, 2, 2, 1, 1, 2, 1}, {12, 2, 2, 1, 1, 2, 2}};
     return v;
 }
-// Before (or without) autotuning: the first of a preference order (four, then two, then
-// one tile per workgroup, double-buffered; the fastest at N = 48-56 when measured) whose
-// grid still has >= 256 workgroups, else the variant with the most workgroups.
+// Before (or without) autotuning: the first of a preference order (control-block records
+// with four, two, one tile per workgroup, then the same tile counts with per-term records;
+// the fastest at N = 56 when measured) whose grid still has >= 256 workgroups, else the
+// variant with the most workgroups.
 template <typename T>
 int default_variant(int L) {
     const auto &v = tiled_variants<T>();
-    for (int pref : {6, 5, 0}) {
+    for (int pref : {10, 9, 8, 6, 5, 0}) {
         const TiledVariant &tv = v.at(pref);
         if (L >= tv.bt + tv.w + 8) return pref;
     }

@@ -151,7 +151,7 @@ def test_apply_h_tiled_smallest_sizes(N, dt, blk):
         assert np.all(np.abs(y - yref) <= K * U24 * mag)
 
 
-N_VARIANTS = 8
+N_VARIANTS = 11
 
 
 @pytest.mark.parametrize("dt", [syk.C128, syk.C64])
@@ -174,6 +174,18 @@ def test_every_tiled_variant(dt, variant):
     syk.krylov_expm(h, 0, 1.5j - 0.6, vd, b, m=30, reorth=2)
     err = (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item()
     assert err <= (1e-10 if dt == syk.C128 else 2e-6)
+
+
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+@pytest.mark.parametrize("variant", [8, 9, 10])
+def test_control_block_variants_split_partner_steps(dt, variant):
+    """Control-block variants on a Hamiltonian with many terms per partner tile (N = 40,
+    K = 1600): partner steps carrying more records than one block holds are split on the
+    host; sampled rows against the oracle, both blocks."""
+    for blk in (0, 1):
+        y, yref, mag, K = _sampled_rows_check(40, 40, 900 + variant, dt, blk, nrows=1500, variant=variant)
+        u = 2.0 ** -52 if dt == syk.C128 else U24
+        assert np.all(np.abs(y - yref) <= K * u * mag)
 
 
 def test_select_variant_rejects_out_of_range():
