@@ -53,7 +53,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
 # plain device copy of known size (profiles/apply_h_tiled_N56_k4_c64_traffic.txt).  Valid
 # only for the kernel revision it was measured on.
-TRAFFIC = {"kernel_rev": "tiled-multi-9", "variant": 6, "fetch_bytes": 27827628113, "write_bytes": 1073886544}
+TRAFFIC = {"kernel_rev": "tiled-block-10", "variant": 10, "fetch_bytes": 27854690717, "write_bytes": 1073876551}
 
 
 def t_grid():
