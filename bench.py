@@ -30,6 +30,18 @@ Also reported, outside the timed region:
   one Haar state, request seed 50000 + id) at a fixed offered rate for a fixed window,
   with p50/p99 submit-to-finish latency and completed realisations per hour.
 
+* apply_k1: apply_H at N = 56 with k = 1 (K = 56), where HBM bandwidth binds, with its
+  algorithmic HBM fraction;
+* derived figures of the timed curve: the VALU-floor fraction of apply_H (one lane
+  instruction per term-amplitude), the measured HBM rate (hardware-counter bytes over the
+  event-timed launch), and the algorithmic HBM fraction of a whole Lanczos iteration (7
+  vector passes: x read, y written and v_{j-1}, v_j read by the fused epilogue, then y,
+  u_j read and u_{j+1} written by the residual pass);
+* cpu_baseline.plain_cpu_lanczos: a plain C/OpenMP complex128 matrix-free Lanczos
+  iteration on the same block (oracle/cpu_lanczos.c), projected to realisations/hour;
+* mixed_precision also times the complex64 path on the same four points, giving the
+  speed ratio over the plain complex128 path at equal OTOC accuracy.
+
 --pmc-sample runs a short chain (one beta, t = 0, 0.25, 0.5) in the identical launch
 configuration plus a 1 GiB device copy, for hardware-counter passes.
 """
@@ -97,6 +109,14 @@ def mixed_precision_check(syk, curve_c64, stream):
                                 m=M_KRYLOV, stream=stream)
     secs = time.perf_counter() - t0
     h.close()
+    # the same four points through the complex64 path, for the speed ratio at equal accuracy
+    h64 = syk.create_hamiltonian(N, 4, K_SPARSITY, SEED)
+    syk.autotune(h64, syk.C64, stream=stream)
+    t1 = time.perf_counter()
+    _, _, _, st64 = syk.otoc(h64, N - 1, N - 2, 10.0, t_check, nvec=1, state_seed=STATE_SEED, dtype=syk.C64,
+                             m=M_KRYLOV, tol=TOL_C64, stream=stream)
+    secs64 = time.perf_counter() - t1
+    h64.close()
     ts = t_grid()
     idx = [ts.index(t) for t in t_check]
     c_raw, c_nrm, c_im = (curve_c64[0][idx], curve_c64[1][idx], curve_c64[2][idx])
@@ -108,8 +128,58 @@ def mixed_precision_check(syk, curve_c64, stream):
             "rel_err_F_imag": [float(abs(a - b)) / scale for a, b in zip(c_im, im)],
             "max_abs_err_F_norm": float(max(abs(a - b) for a, b in zip(c_nrm, nrm))),
             "tolerance_F_norm": 1e-5, "c128_seconds": secs, "c128_matvecs": st["matvecs"],
+            "c64_seconds_same_points": secs64, "c64_matvecs_same_points": st64["matvecs"],
+            "c64_speedup_over_c128": secs / secs64,
             "note": "raw F carries the e^{-beta H} weights of an unnormalised state; errors of F_raw and F_imag "
                     "are relative to |F_raw(0)|"}
+
+
+def apply_k1_leg(syk, stream):
+    """apply_H at N = 56 with k = 1 (K = 56), where HBM bandwidth binds: the autotuner's
+    per-variant times of a plain apply, best variant."""
+    h = syk.create_hamiltonian(N, 4, 1.0, SEED)
+    syk.autotune(h, syk.C64, stream=stream)
+    variant, ms = syk.autotune(h, syk.C64, stream=stream)
+    info = h.info()
+    h.close()
+    best = min(m for m in ms if m > 0)
+    n = info["block_dim"]
+    alg = 2.0 * n * 8
+    return {"K": info["K"], "variant": variant, "ms": best, "term_amps_per_s": info["K"] * n / (best * 1e-3),
+            "algorithmic_hbm_TBps": alg / (best * 1e-3) / 1e12,
+            "algorithmic_hbm_frac": alg / (best * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "variant_ms": ms, "note": "plain apply (read x once, write y once), complex64, seed 56"}
+
+
+def cpu_lanczos_leg(matvecs_per_realisation: float, steps: int = 1):
+    """Plain C/OpenMP matrix-free complex128 Lanczos (oracle/cpu_lanczos.c) on the N = 56 U
+    block: one iteration timed, the realisation rate projected from the per-iteration time."""
+    import numpy as np
+
+    from oracle import cpu_lanczos, ensemble, matfree
+    subs, J, _ = ensemble.sample_terms(N, K_SPARSITY, SEED)
+    xzc = cpu_lanczos.xz_terms(matfree.block_terms(N, subs, J, 0))
+    L = N // 2 - 1
+    rng = np.random.default_rng(2)
+    v0 = np.empty(1 << L, dtype=np.complex128)
+    v0.real = rng.standard_normal(1 << L)
+    v0.imag = rng.standard_normal(1 << L)
+    a, b, t_apply, t_total, thr = cpu_lanczos.lanczos(L, xzc, v0, steps)
+    del v0
+    t_iter = t_total / steps
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return {"value_projected": 3600.0 / (matvecs_per_realisation * t_iter), "unit": "realisations/h",
+            "threads": thr, "nproc": os.cpu_count(), "cpu_model": model,
+            "seconds_per_matvec": t_apply / steps, "seconds_per_iteration": t_iter,
+            "term_amps_per_s": len(xzc[0]) * (1 << L) / (t_apply / steps),
+            "sample": f"{steps} Lanczos iterations on the N=56 K=224 U block in complex128 (plain C, OpenMP, "
+                      f"no tiling), projected by {matvecs_per_realisation:.0f} matvecs per realisation "
+                      f"measured on the GPU"}
 
 
 def batched_leg(syk, n_real=512, seed=3000):
@@ -252,6 +322,8 @@ def main():
     alg_bytes = 2.0 * n * 8                   # read x once, write y once (complex64)
     achieved_tflops = flops / avg_s / 1e12
     value = 3600.0 * args.steps / (3.0 * elapsed)
+    t_iter = elapsed / max(matvecs, 1)                      # wall time per Lanczos iteration
+    valu_floor_s = term_amps / 3.93e13                      # one VALU lane-instruction per term-amp
     term_amps_per_real = 3.0 * matvecs / args.steps * term_amps
     lib_rev = syk.kernel_revision()
     traffic = None
@@ -279,6 +351,10 @@ def main():
         "apply_H_term_amps_per_s": term_amps / avg_s,
         "apply_H_ms": avg_s * 1e3,
         "apply_H_algorithmic_hbm_frac": alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS,
+        "apply_H_valu_floor_frac": valu_floor_s / avg_s,
+        "apply_H_measured_hbm_TBps": (traffic / avg_s / 1e12) if traffic else None,
+        "lanczos_iteration_ms": t_iter * 1e3,
+        "lanczos_iteration_algorithmic_hbm_frac": 7.0 * n * 8 / t_iter / 1e9 / HBM_PEAK_GBS,
         "matvecs_per_curve": matvecs / args.steps,
         "kernel": {"revision": lib_rev, "variant": variant, "variant_ms": variant_ms, "plan": plan},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
@@ -292,6 +368,10 @@ def main():
         syk.release_workspace()
         rec["mixed_precision"] = mixed_precision_check(syk, c10[0], stream)
         syk.release_workspace()
+    if not args.no_precision:
+        print("[bench] apply_H at k = 1", file=sys.stderr, flush=True)
+        rec["apply_k1"] = apply_k1_leg(syk, stream)
+        syk.release_workspace()
     if not args.no_batched:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         rec["batched"] = batched_leg(syk)
@@ -300,6 +380,8 @@ def main():
         rec["serving"] = serving_leg(syk)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(term_amps_per_real)
+        print("[bench] plain CPU matrix-free Lanczos", file=sys.stderr, flush=True)
+        rec["cpu_baseline"]["plain_cpu_lanczos"] = cpu_lanczos_leg(3.0 * matvecs / args.steps)
     print(json.dumps(rec), flush=True)
 
 

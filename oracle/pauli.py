@@ -151,3 +151,17 @@ def operator_dense(L: int, xs, zs, cs) -> np.ndarray:
     for x, z, c in zip(xs, zs, cs):
         M += c * dense(from_xz(L, int(x), int(z)))
     return M
+
+
+def to_xz(labels):
+    """Inverse of from_xz: a label string P = (x) sigma_q as (x, z, p) with P = i^p X^x Z^z
+    (per qubit Y = i X Z)."""
+    x = z = 0
+    ny = 0
+    for q, lab in enumerate(labels):
+        if lab in (X, Y):
+            x |= 1 << q
+        if lab in (Y, Z):
+            z |= 1 << q
+        ny += lab == Y
+    return x, z, ny % 4
