@@ -103,8 +103,15 @@ void otoc_batch(const syk_batch_item *items, int n_items, const double *t, int n
         lmax = std::max(lmax, h.L);
         for (int blk = 0; blk < 2; ++blk) {
             jb.term_off[blk] = static_cast<uint32_t>(terms.size());
+            std::vector<BatchTerm> bts;
             for (const BlockTerm &bt : h.block_terms[blk])
-                terms.push_back(BatchTerm{bt.x, bt.z, static_cast<float>(bt.c), bt.imag ? 1u : 0u});
+                bts.push_back(BatchTerm{bt.x, bt.z, static_cast<float>(bt.c), bt.imag ? 1u : 0u});
+            std::stable_sort(bts.begin(), bts.end(), [](const BatchTerm &a, const BatchTerm &b) { return a.x < b.x; });
+            for (uint32_t g = 0, t = 0; g <= 8; ++g) {
+                while (t < bts.size() && (bts[t].x >> 12) < g) ++t;
+                jb.gstart[blk][g] = static_cast<uint16_t>(g == 8 ? bts.size() : t);
+            }
+            terms.insert(terms.end(), bts.begin(), bts.end());
         }
         majorana_form(it.N, it.i, jb.wx, jb.wz, jb.ww, jb.w_top);
         majorana_form(it.N, it.j, jb.vx, jb.vz, jb.vw, jb.v_top);

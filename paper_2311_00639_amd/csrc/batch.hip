@@ -77,6 +77,7 @@ struct Ctx {
     float2 *basis;                     // (m + 1) vectors
     float2 *vec[4];                    // l, r2, r4, tmp
     uint32_t tid;
+    const BatchTerm *lterms[2];        // the job's terms staged in LDS (null: read from memory)
     long long matvecs = 0;
     int substeps = 0;
     int status = 0;
@@ -140,8 +141,23 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) 
     static_assert(NCH >= 1 && NCH <= 4 && RC >= 1 && RC <= 16, "chunking");
     const uint32_t tid = c.tid;
     const BatchTerm *terms = c.p.terms + c.job.term_off[blk];
+    const BatchTerm *lterms = c.lterms[blk];
     const int K = c.job.K;
     double dre = 0.0;
+    // one term with wave-uniform fields (scalar registers)
+    auto term = [&](float2 (&acc)[RC], uint32_t tx, uint32_t tz, float tc, uint32_t timag, int o) __attribute__((always_inline)) {
+        const uint32_t xl = tx & (CH - 1);
+        const uint32_t lane = tid ^ (xl & (NT - 1));
+        const uint32_t xr = xl >> LNT;
+        const uint32_t zr = (tz >> LNT) & (RC - 1);
+        // sign of output m = (o RC + r) NT + tid: thread bits, chunk bits, register bits
+        const uint32_t par = (__popc(tid & tz & (NT - 1)) + __popc((tz >> LCH) & static_cast<uint32_t>(o))) & 1u;
+        const float cl = fsign(tc, par);
+        if (timag)
+            term_regs<NT, RC, true>(acc, c.buf, cl, lane, xr, zr);
+        else
+            term_regs<NT, RC, false>(acc, c.buf, cl, lane, xr, zr);
+    };
     for (int o = 0; o < NCH; ++o) {
         float2 acc[RC];
 #pragma unroll
@@ -151,21 +167,26 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) 
 #pragma unroll
             for (int r = 0; r < RC; ++r) c.buf[r * NT + tid] = v[ch * CH + r * NT + tid];
             __syncthreads();
+            // the terms with partner chunk offset x >> LCH == o ^ ch (terms sorted by x)
             const uint32_t want = static_cast<uint32_t>(o ^ ch);
-            for (int t = 0; t < K; ++t) {
-                const BatchTerm tm = terms[t];
-                if ((tm.x >> LCH) != want) continue;
-                const uint32_t xl = tm.x & (CH - 1);
-                const uint32_t lane = tid ^ (xl & (NT - 1));
-                const uint32_t xr = xl >> LNT;
-                const uint32_t zr = (tm.z >> LNT) & (RC - 1);
-                // sign of output m = (o RC + r) NT + tid: thread bits, chunk bits, register bits
-                const uint32_t par = (__popc(tid & tm.z & (NT - 1)) + __popc((tm.z >> LCH) & static_cast<uint32_t>(o))) & 1u;
-                const float cl = fsign(tm.c, par);
-                if (tm.imag)
-                    term_regs<NT, RC, true>(acc, c.buf, cl, lane, xr, zr);
-                else
-                    term_regs<NT, RC, false>(acc, c.buf, cl, lane, xr, zr);
+            int lo = 0, hi = K;
+            if constexpr (L >= 12) {
+                constexpr int SH = LCH - 12;
+                lo = c.job.gstart[blk][want << SH];
+                hi = c.job.gstart[blk][(want + 1) << SH];
+            }
+            if (lterms) {
+                for (int t = lo; t < hi; ++t) {
+                    const BatchTerm tm = lterms[t];
+                    term(acc, __builtin_amdgcn_readfirstlane(tm.x), __builtin_amdgcn_readfirstlane(tm.z),
+                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tm.c))),
+                         __builtin_amdgcn_readfirstlane(tm.imag), o);
+                }
+            } else {
+                for (int t = lo; t < hi; ++t) {
+                    const BatchTerm tm = terms[t];
+                    term(acc, tm.x, tm.z, tm.c, tm.imag, o);
+                }
             }
         }
 #pragma unroll
@@ -561,6 +582,10 @@ __global__ void __launch_bounds__(NT, OCC * NT / 256) otoc_batch_kernel(BatchPar
     __shared__ Shared<NT> sh;
     __shared__ float2 buf[1 << CHB];
     __shared__ int job_sh;
+    // term staging for the job (both blocks), where LDS allows: jobs with more terms read
+    // them from memory
+    constexpr int TL = NT >= 512 ? 256 : 1;
+    __shared__ BatchTerm tl[2][TL];
     const uint32_t tid = threadIdx.x;
     for (int j = tid; j < 4 * kCheb; j += NT) sh.cosb[j] = cos(M_PI * j / (2.0 * kCheb));
     float2 *slot = p.ws + static_cast<size_t>(blockIdx.x) * p.slot_stride;
@@ -578,7 +603,14 @@ __global__ void __launch_bounds__(NT, OCC * NT / 256) otoc_batch_kernel(BatchPar
                                                slot + static_cast<size_t>(p.m + 2) * p.vec_stride,
                                                slot + static_cast<size_t>(p.m + 3) * p.vec_stride,
                                                slot + static_cast<size_t>(p.m + 4) * p.vec_stride},
-                       tid};
+                       tid, {nullptr, nullptr}};
+        if (TL > 1 && jb.K <= TL) {
+            for (int blk = 0; blk < 2; ++blk)
+                for (int t = static_cast<int>(tid); t < jb.K; t += NT) tl[blk][t] = p.terms[jb.term_off[blk] + t];
+            __syncthreads();
+            c.lterms[0] = tl[0];
+            c.lterms[1] = tl[1];
+        }
         // the block size is a compile-time parameter of the job code
         switch (jb.L) {
 #define SYK_BL(LL)                                                       \

@@ -26,6 +26,10 @@ struct BatchJob {
     int vw, v_top;
     uint64_t base;                      // Haar generator base of this vector
     double beta;
+    // each block's terms are sorted by x; gstart[blk][g] = first term with x >> 12 >= g
+    // (g <= 8; gstart[blk][8] = K), so the terms of one partner chunk are contiguous
+    uint16_t gstart[2][9];
+    uint16_t pad2[2];
 };
 
 struct BatchParams {
