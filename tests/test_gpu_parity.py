@@ -196,11 +196,15 @@ def test_select_variant_rejects_out_of_range():
     assert n == N_VARIANTS
 
 
-def test_apply_h_tiled_many_vectors_padded():
-    """nvec = 3 vectors at a padded leading dimension through the tiled kernel (N = 40)."""
+@pytest.mark.parametrize("variant", [None, 8, 10])
+def test_apply_h_tiled_many_vectors_padded(variant):
+    """nvec = 3 vectors at a padded leading dimension through the tiled kernel (N = 40):
+    the default variant and control-block variants with one and four tiles per workgroup."""
     N, k, seed = 40, 4, 12
     subs, J, _ = ensemble.sample_terms(N, k, seed)
     h = syk.create_hamiltonian(N, 4, k, seed)
+    if variant is not None:
+        syk.select_variant(h, syk.C64, variant)
     n = 1 << (N // 2 - 1)
     nvec, ld = 3, n + 1000
     X = torch.zeros(nvec, ld, dtype=torch.complex64, device="cuda")
@@ -218,6 +222,49 @@ def test_apply_h_tiled_many_vectors_padded():
         yref = matfree.apply_rows(terms, lambda idx: xr[idx.astype(np.int64)], rows)
         assert rel(Yh[v, rows.astype(np.int64)], yref) <= 4e-6
     assert np.all(Yh[:, n:] == 2.0)
+
+
+def _device_sampled_rows(N, k, seed, dt, nrows, blk=0):
+    """apply_H at large N on a device-generated vector; rows recomputed by the oracle from
+    the vector's entries gathered at the partner indices."""
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    n = 1 << (N // 2 - 1)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    xd = torch.randn(n, dtype=cdt(dt), device="cuda", generator=g)
+    yd = torch.empty_like(xd)
+    syk.apply_H(h, blk, xd, yd)
+    torch.cuda.synchronize()
+    rows = inputs.row_sample(n, nrows, seed + 2)
+    y = host(yd[torch.from_numpy(rows.astype(np.int64)).to("cuda")])
+    del yd
+
+    def x_at(idx):
+        return host(xd[torch.from_numpy(np.asarray(idx, dtype=np.int64)).to("cuda")])
+
+    terms = matfree.block_terms(N, subs, J, blk)
+    yref = matfree.apply_rows(terms, x_at, rows)
+    flips = [(tuple(pauli.X if lab in (pauli.X, pauli.Y) else pauli.I for lab in labels), abs(c))
+             for labels, c in terms]
+    mag = matfree.apply_rows(flips, lambda idx: np.abs(x_at(idx)), rows).real
+    del xd
+    torch.cuda.empty_cache()
+    return y, yref, mag, len(subs)
+
+
+def test_apply_h_largest_block_N64_c64():
+    """The largest block the library takes: N = 64, 2^31 complex64 amplitudes (16 GiB per
+    vector), k = 4 (K = 256), tiled kernel, on sampled rows with the accumulation bound."""
+    y, yref, mag, K = _device_sampled_rows(64, 4, 64, syk.C64, 300)
+    assert np.all(np.abs(y - yref) <= K * U24 * mag)
+    assert rel(y, yref) <= 4e-6
+
+
+def test_apply_h_large_block_N60_c128():
+    """N = 60 in complex128 (2^29 amplitudes, 8 GiB per vector), block D, sampled rows."""
+    y, yref, mag, K = _device_sampled_rows(60, 2, 60, syk.C128, 300, blk=1)
+    assert np.all(np.abs(y - yref) <= K * 2.0 ** -52 * mag)
+    assert rel(y, yref) <= 1e-12
 
 
 def test_apply_h_hermitian_N40():
