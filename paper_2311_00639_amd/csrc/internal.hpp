@@ -214,9 +214,6 @@ void launch_lanczos_normalize(T *w, const double *beta, uint64_t n, hipStream_t 
 // beta^2 = ||w - alpha_re v||^2 at beta2_out (expanded in the sums)
 void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_out, double *beta2_out,
                             hipStream_t s);
-// w <- (w - alpha_re v) / beta, beta = sqrt(beta2[0]); zero if beta underflows
-template <typename T>
-void launch_lanczos_update(T *w, const T *v, const double *alpha, const double *beta2, uint64_t n, hipStream_t s);
 // fused path: w <- w - alpha_j s_j u_j (v = u_j, s_j from beta2[j], j >= 1; 1 for j = 0) and
 // per-block partials of ||w||^2 (reduction_blocks(n) of them)
 template <typename T>

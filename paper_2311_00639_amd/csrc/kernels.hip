@@ -360,30 +360,6 @@ void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_ou
     SYK_HIP(hipGetLastError());
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock) lanczos_update(V2<T> *__restrict__ w, const V2<T> *__restrict__ v,
-                                                         const double *__restrict__ alpha,
-                                                         const double *__restrict__ beta2, uint64_t n) {
-    const double b = sqrt(beta2[0]);
-    const T inv = (b > 1e-300) ? static_cast<T>(1.0 / b) : T(0);
-    const T al = static_cast<T>(alpha[0]);
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
-         i += static_cast<uint64_t>(gridDim.x) * kBlock) {
-        V2<T> u = w[i];
-        const V2<T> c = v[i];
-        u.x = (u.x - al * c.x) * inv;
-        u.y = (u.y - al * c.y) * inv;
-        w[i] = u;
-    }
-}
-
-template <typename T>
-void launch_lanczos_update(T *w, const T *v, const double *alpha, const double *beta2, uint64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(lanczos_update<T>, dim3(grid_for(n, 4)), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(w),
-                       reinterpret_cast<const V2<T> *>(v), alpha, beta2, n);
-    SYK_HIP(hipGetLastError());
-}
-
 // fused Lanczos: w <- w - (alpha_j / ||u_j||) u_j, with partials of ||w||^2
 template <typename T>
 __global__ void __launch_bounds__(kBlock) lanczos_residual(V2<T> *__restrict__ w, const V2<T> *__restrict__ v,
@@ -526,7 +502,6 @@ void launch_subtract_proj(T *w, const T *basis, uint64_t stride, int nb, const d
                                           hipStream_t);                                                            \
     template void launch_lanczos_orth2<T>(T *, const T *, const double *, uint64_t, double *, int, hipStream_t);   \
     template void launch_lanczos_normalize<T>(T *, const double *, uint64_t, hipStream_t);                         \
-    template void launch_lanczos_update<T>(T *, const T *, const double *, const double *, uint64_t, hipStream_t); \
     template void launch_lanczos_residual<T>(T *, const T *, const double *, const double *, int, uint64_t,          \
                                              double *, hipStream_t);                                            \
     template void launch_scale_copy<T>(const T *, T *, uint64_t, double, hipStream_t);                             \
