@@ -3,19 +3,22 @@
 // y[m] = sum_a c_a i^{imag_a} (-1)^{popc(m & z_a)} x[m ^ x_a]   (supplement Algorithm 1, with the
 // sign parity of x_a & z_a folded into c_a).
 //
-// Data flow.  A workgroup owns one output tile of 2^BT consecutive amplitudes, held in
-// registers: thread t keeps outputs r * NT + t, r < R.  Terms are grouped on the host by
-// g = x_a >> BT, so every term of a group reads the same partner tile T ^ g.  For each
-// group the partner tile is copied once into LDS by direct global-to-LDS loads (the next
-// groups' tiles stream into other LDS buffers while the current one is consumed) and
-// every term of the group reads it with an XOR-permuted index: the thread bits of x_a permute the lane's
-// LDS address once per term, the register bits add a wave-uniform offset per read.  The
-// tile and thread parts of the sign are folded into the coefficient once per term; the
-// register part is a wave-uniform select per read, so an amplitude costs one LDS read,
-// one address add, one select and two FMAs.  The host planner (apply_plan.cpp) maps
-// workgroups to tiles so that the tiles resident on one XCD form a coset of a subspace
-// that many partner offsets differ by, and orders groups class by class, so a partner
-// tile fetched for one workgroup is re-read from L2 by others.
+// Data flow.  A workgroup owns 2^W output tiles of 2^BT consecutive amplitudes (a coset
+// t0 ^ span(h) of the tile index space), held in registers: thread t keeps outputs
+// r * NT + t, r < R, of each.  Terms are grouped on the host by g = x_a >> BT, so every term
+// of a group reads the same partner tile T ^ g.  The workgroup streams the union of its
+// tiles' partner tiles once: each partner tile is copied into LDS by direct global-to-LDS
+// loads (the next one streams into the other buffer while the current one is consumed), and
+// every term that needs it reads it with an XOR-permuted index: the thread bits of x_a
+// permute the lane's LDS address once per term, the register bits give one address per
+// register read.  The tile and thread parts of the sign are folded into the coefficient once
+// per term, the register part is one sign operation per read, so an amplitude costs one LDS
+// read, one address operation, one sign operation and two FMAs.  Term data comes either from
+// per-term records (scalar loads) or from per-step control blocks held in a VGPR and read
+// with readlane (no scalar loads in the term loop).  The host planner (apply_plan.cpp) maps
+// workgroups to tiles so that the tiles resident on one XCD form a coset of a subspace that
+// many partner offsets differ by, and orders partner steps class by class, so a partner tile
+// fetched for one workgroup is re-read from L2 by others.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
