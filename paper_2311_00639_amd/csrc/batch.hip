@@ -25,6 +25,35 @@ namespace syk {
 
 namespace {
 
+// Explicit address spaces.  The job code runs in out-of-line functions, where pointers that
+// are not typed by address space turn into generic (flat) accesses: slower for LDS, and each
+// one waits on both memory counters.
+typedef __attribute__((address_space(1))) float2 gf2;          // device memory
+typedef __attribute__((address_space(3))) float2 lf2;          // LDS
+typedef __attribute__((address_space(1))) const BatchTerm gterm;
+typedef __attribute__((address_space(3))) const BatchTerm lterm;
+
+// loads and stores through typed pointers use clang's builtin vector types (the HIP vector
+// classes cannot be copied from address-space-qualified objects)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 ld(const gf2 *p) {
+    const f32x2 u = *(__attribute__((address_space(1))) const f32x2 *)p;
+    return float2{u.x, u.y};
+}
+__device__ __forceinline__ void st(gf2 *p, float2 v) { *(__attribute__((address_space(1))) f32x2 *)p = f32x2{v.x, v.y}; }
+__device__ __forceinline__ float2 ld(const lf2 *p) {
+    const f32x2 u = *(__attribute__((address_space(3))) const f32x2 *)p;
+    return float2{u.x, u.y};
+}
+__device__ __forceinline__ void st(lf2 *p, float2 v) { *(__attribute__((address_space(3))) f32x2 *)p = f32x2{v.x, v.y}; }
+__device__ __forceinline__ BatchTerm ld(gterm *p) {
+    return __builtin_bit_cast(BatchTerm, *(__attribute__((address_space(1))) const u32x4 *)p);
+}
+__device__ __forceinline__ BatchTerm ld(lterm *p) {
+    return __builtin_bit_cast(BatchTerm, *(__attribute__((address_space(3))) const u32x4 *)p);
+}
+
 constexpr int kCheb = 64;               // Chebyshev nodes and series length
 constexpr double kMaxArg = 25.0;        // largest |w| b evaluated
 
@@ -67,17 +96,20 @@ struct Shared {
     int ctl_i[4];
 };
 
+template <int NT>
+using LShared = __attribute__((address_space(3))) Shared<NT>;
+
 // whole-workgroup context of one job
 template <int NT, int CHB>
 struct Ctx {
     const BatchParams &p;
-    Shared<NT> &sh;
-    float2 *buf;                       // LDS staging, 2^CHB amplitudes
+    LShared<NT> &sh;
+    lf2 *buf;                          // LDS staging, 2^CHB amplitudes
     const BatchJob &job;
-    float2 *basis;                     // (m + 1) vectors
-    float2 *vec[4];                    // l, r2, r4, tmp
+    gf2 *basis;                        // (m + 1) vectors
+    gf2 *vec[4];                       // l, r2, r4, tmp
     uint32_t tid;
-    const BatchTerm *lterms[2];        // the job's terms staged in LDS (null: read from memory)
+    lterm *lterms[2];                  // the job's terms staged in LDS (null: read from memory)
     long long matvecs = 0;
     int substeps = 0;
     int status = 0;
@@ -85,7 +117,7 @@ struct Ctx {
 
 // sum of two doubles over the workgroup, same value and order in every thread
 template <int NT>
-__device__ __forceinline__ void bsum2(double &a, double &b, Shared<NT> &sh, uint32_t tid) {
+__device__ __forceinline__ void bsum2(double &a, double &b, LShared<NT> &sh, uint32_t tid) {
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_xor(a, off, 64);
         b += __shfl_xor(b, off, 64);
@@ -109,12 +141,12 @@ __device__ __forceinline__ void bsum2(double &a, double &b, Shared<NT> &sh, uint
 // Thread tid owns amplitudes r * NT + tid, r < R = 2^L / NT.
 
 template <int NT, int RC, bool IM>
-__device__ __forceinline__ void term_regs(float2 (&acc)[RC], const float2 *buf, float cl, uint32_t lane, uint32_t xr,
+__device__ __forceinline__ void term_regs(float2 (&acc)[RC], const lf2 *buf, float cl, uint32_t lane, uint32_t xr,
                                           uint32_t zr) {
     constexpr int LNT = __builtin_ctz(NT);
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-        const float2 q = buf[((static_cast<uint32_t>(r) ^ xr) << LNT) | lane];
+        const float2 q = ld(buf + (((static_cast<uint32_t>(r) ^ xr) << LNT) | lane));
         const float cr = fsign(cl, __popc(static_cast<uint32_t>(r) & zr) & 1u);
         if (IM) {
             acc[r].x -= cr * q.y;
@@ -131,7 +163,7 @@ __device__ __forceinline__ void term_regs(float2 (&acc)[RC], const float2 *buf, 
 // registers (RC per thread) while every chunk ch of v is staged in LDS in turn, and the
 // terms whose partner offset x >> log2(CH) equals o ^ ch are applied from it.
 template <int NT, int CHB, int L>
-__device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) {
+__device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
     constexpr int n = 1 << L;
     constexpr int LCH = L < CHB ? L : CHB;
     constexpr int CH = 1 << LCH;
@@ -140,8 +172,8 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) 
     constexpr int LNT = __builtin_ctz(NT);
     static_assert(NCH >= 1 && NCH <= 4 && RC >= 1 && RC <= 16, "chunking");
     const uint32_t tid = c.tid;
-    const BatchTerm *terms = c.p.terms + c.job.term_off[blk];
-    const BatchTerm *lterms = c.lterms[blk];
+    gterm *terms = (gterm *)(c.p.terms + c.job.term_off[blk]);
+    lterm *lterms = c.lterms[blk];
     const int K = c.job.K;
     double dre = 0.0;
     // one term with wave-uniform fields (scalar registers)
@@ -165,7 +197,7 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) 
         for (int ch = 0; ch < NCH; ++ch) {
             __syncthreads();                              // earlier readers of buf are done
 #pragma unroll
-            for (int r = 0; r < RC; ++r) c.buf[r * NT + tid] = v[ch * CH + r * NT + tid];
+            for (int r = 0; r < RC; ++r) st(c.buf + (r * NT + tid), ld(v + (ch * CH + r * NT + tid)));
             __syncthreads();
             // the terms with partner chunk offset x >> LCH == o ^ ch (terms sorted by x)
             const uint32_t want = static_cast<uint32_t>(o ^ ch);
@@ -177,14 +209,14 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) 
             }
             if (lterms) {
                 for (int t = lo; t < hi; ++t) {
-                    const BatchTerm tm = lterms[t];
+                    const BatchTerm tm = ld(lterms + t);
                     term(acc, __builtin_amdgcn_readfirstlane(tm.x), __builtin_amdgcn_readfirstlane(tm.z),
                          __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tm.c))),
                          __builtin_amdgcn_readfirstlane(tm.imag), o);
                 }
             } else {
                 for (int t = lo; t < hi; ++t) {
-                    const BatchTerm tm = terms[t];
+                    const BatchTerm tm = ld(terms + t);
                     term(acc, tm.x, tm.z, tm.c, tm.imag, o);
                 }
             }
@@ -192,21 +224,21 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const float2 *v, float2 *y) 
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
             const int i = o * CH + r * NT + static_cast<int>(tid);
-            const float2 q = v[i];
+            const float2 q = ld(v + i);
             dre += static_cast<double>(q.x) * acc[r].x + static_cast<double>(q.y) * acc[r].y;
-            y[i] = acc[r];
+            st(y + i, acc[r]);
         }
     }
     return dre;
 }
 
 template <int NT, int CHB, int L>
-__device__ double norm2(Ctx<NT, CHB> &c, const float2 *v) {
+__device__ double norm2(Ctx<NT, CHB> &c, const gf2 *v) {
     constexpr int R = (1 << L) / NT;
     double a = 0.0, b = 0.0;
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
-        const float2 q = v[r * NT + c.tid];
+        const float2 q = ld(v + (r * NT + c.tid));
         a += static_cast<double>(q.x) * q.x + static_cast<double>(q.y) * q.y;
     }
     bsum2<NT>(a, b, c.sh, c.tid);
@@ -215,12 +247,12 @@ __device__ double norm2(Ctx<NT, CHB> &c, const float2 *v) {
 
 // <u, v> = sum conj(u) v
 template <int NT, int CHB, int L>
-__device__ double2 dot(Ctx<NT, CHB> &c, const float2 *u, const float2 *v) {
+__device__ double2 dot(Ctx<NT, CHB> &c, const gf2 *u, const gf2 *v) {
     constexpr int R = (1 << L) / NT;
     double a = 0.0, b = 0.0;
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
-        const float2 p = u[r * NT + c.tid], q = v[r * NT + c.tid];
+        const float2 p = ld(u + (r * NT + c.tid)), q = ld(v + (r * NT + c.tid));
         a += static_cast<double>(p.x) * q.x + static_cast<double>(p.y) * q.y;
         b += static_cast<double>(p.x) * q.y - static_cast<double>(p.y) * q.x;
     }
@@ -229,20 +261,20 @@ __device__ double2 dot(Ctx<NT, CHB> &c, const float2 *u, const float2 *v) {
 }
 
 template <int NT, int CHB, int L>
-__device__ void scale_copy(Ctx<NT, CHB> &c, const float2 *src, float2 *dst, double s) {
+__device__ void scale_copy(Ctx<NT, CHB> &c, const gf2 *src, gf2 *dst, double s) {
     constexpr int R = (1 << L) / NT;
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
-        const float2 q = src[r * NT + c.tid];
-        dst[r * NT + c.tid] = float2{static_cast<float>(s * q.x), static_cast<float>(s * q.y)};
+        const float2 q = ld(src + (r * NT + c.tid));
+        st(dst + (r * NT + c.tid), float2{static_cast<float>(s * q.x), static_cast<float>(s * q.y)});
     }
     __syncthreads();
 }
 
 // dst = chi block map of Majorana n from block `src_blk` (times sqrt 2: the Pauli string)
 template <int NT, int CHB, int L>
-__device__ void gamma(Ctx<NT, CHB> &c, bool top, uint32_t x, uint32_t z, int w, int src_blk, const float2 *src,
-                      float2 *dst) {
+__device__ void gamma(Ctx<NT, CHB> &c, bool top, uint32_t x, uint32_t z, int w, int src_blk, const gf2 *src,
+                      gf2 *dst) {
     constexpr int R = (1 << L) / NT;
     // scale i^w, or +-i for n = N - 1 (U -> D: +i, D -> U: -i)
     int q = top ? (src_blk == 0 ? 1 : 3) : (w & 3);
@@ -254,7 +286,7 @@ __device__ void gamma(Ctx<NT, CHB> &c, bool top, uint32_t x, uint32_t z, int w, 
     for (int r = 0; r < R; ++r) {
         const uint32_t m = static_cast<uint32_t>(r * NT) + c.tid;
         const uint32_t k = m ^ x;
-        float2 v = src[k];
+        float2 v = ld(src + k);
         if (__popc(k & z) & 1) v = float2{-v.x, -v.y};
         float2 o;
         switch (q) {
@@ -263,14 +295,14 @@ __device__ void gamma(Ctx<NT, CHB> &c, bool top, uint32_t x, uint32_t z, int w, 
             case 2: o = float2{-v.x, -v.y}; break;
             default: o = float2{v.y, -v.x}; break;
         }
-        dst[m] = o;
+        st(dst + m, o);
     }
     __syncthreads();
 }
 
 // Haar state of this job's vector: block A part into dst, normalised over the full space
 template <int NT, int CHB, int L>
-__device__ void haar(Ctx<NT, CHB> &c, int A, float2 *dst) {
+__device__ void haar(Ctx<NT, CHB> &c, int A, gf2 *dst) {
     constexpr int R = (1 << L) / NT;
     const uint64_t h = 1ULL << L;
     double a = 0.0, b = 0.0;
@@ -281,7 +313,7 @@ __device__ void haar(Ctx<NT, CHB> &c, int A, float2 *dst) {
         const double2 d = bhaar(c.job.base, h + m);
         a += u.x * u.x + u.y * u.y + d.x * d.x + d.y * d.y;
         const double2 s = A == 0 ? u : d;
-        dst[m] = float2{static_cast<float>(s.x), static_cast<float>(s.y)};
+        st(dst + m, float2{static_cast<float>(s.x), static_cast<float>(s.y)});
     }
     bsum2<NT>(a, b, c.sh, c.tid);
     const double inv = 1.0 / sqrt(a);
@@ -289,7 +321,7 @@ __device__ void haar(Ctx<NT, CHB> &c, int A, float2 *dst) {
     for (int r = 0; r < R; ++r) {
         const uint64_t m = static_cast<uint64_t>(r * NT + c.tid);
         const double2 u = A == 0 ? bhaar(c.job.base, m) : bhaar(c.job.base, h + m);
-        dst[m] = float2{static_cast<float>(u.x * inv), static_cast<float>(u.y * inv)};
+        st(dst + m, float2{static_cast<float>(u.x * inv), static_cast<float>(u.y * inv)});
     }
     __syncthreads();
 }
@@ -299,9 +331,9 @@ __device__ void haar(Ctx<NT, CHB> &c, int A, float2 *dst) {
 template <int NT, int CHB, int L>
 __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
     constexpr int R = (1 << L) / NT;
-    const float2 *vj = c.basis + static_cast<size_t>(j) * c.p.vec_stride;
-    const float2 *vp = j > 0 ? c.basis + static_cast<size_t>(j - 1) * c.p.vec_stride : nullptr;
-    float2 *vn = c.basis + static_cast<size_t>(j + 1) * c.p.vec_stride;
+    const gf2 *vj = c.basis + static_cast<size_t>(j) * c.p.vec_stride;
+    const gf2 *vp = j > 0 ? c.basis + static_cast<size_t>(j - 1) * c.p.vec_stride : nullptr;
+    gf2 *vn = c.basis + static_cast<size_t>(j + 1) * c.p.vec_stride;
     double a = apply_h<NT, CHB, L>(c, blk, vj, vn), dummy = 0.0;
     bsum2<NT>(a, dummy, c.sh, c.tid);
     const double alpha = a;
@@ -312,16 +344,16 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
         const int i = r * NT + static_cast<int>(c.tid);
-        const float2 q = vj[i];
-        float2 w = vn[i];
+        const float2 q = ld(vj + i);
+        float2 w = ld(vn + i);
         w.x -= fa * q.x;
         w.y -= fa * q.y;
         if (vp) {
-            const float2 p = vp[i];
+            const float2 p = ld(vp + i);
             w.x -= fb * p.x;
             w.y -= fb * p.y;
         }
-        vn[i] = w;
+        st(vn + i, w);
         w2 += static_cast<double>(w.x) * w.x + static_cast<double>(w.y) * w.y;
     }
     bsum2<NT>(w2, dummy, c.sh, c.tid);
@@ -330,8 +362,8 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
         const int i = r * NT + static_cast<int>(c.tid);
-        const float2 w = vn[i];
-        vn[i] = float2{w.x * inv, w.y * inv};
+        const float2 w = ld(vn + i);
+        st(vn + i, float2{w.x * inv, w.y * inv});
     }
     if (c.tid == 0) {
         c.sh.al[j] = alpha;
@@ -343,7 +375,7 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
 // Wavefront 0 only.  c = e^{(wr + i wi) T_k} e_1 into sh.cre / sh.cim; returns |c_{k-1}|,
 // or a negative value when the argument exceeds the evaluated range.
 template <int NT>
-__device__ double small_exp(Shared<NT> &sh, int k, double wr, double wi, uint32_t lane) {
+__device__ double small_exp(LShared<NT> &sh, int k, double wr, double wi, uint32_t lane) {
     // Gershgorin interval of T_k (off-diagonal bt[1..k-1])
     double lo = 1e300, hi = -1e300;
     if (static_cast<int>(lane) < k) {
@@ -426,7 +458,7 @@ __device__ double small_exp(Shared<NT> &sh, int k, double wr, double wi, uint32_
 // Step decision after k Lanczos vectors (wavefront 0): ctl_i[0] = 1 if the sub-step ends
 // here, ctl_d[0] = its fraction tau, ctl_i[1] = error; cre/cim hold e^{tau z T} e_1.
 template <int NT>
-__device__ void decide(Shared<NT> &sh, int k, int m, double remaining, double zr, double zi, double tol,
+__device__ void decide(LShared<NT> &sh, int k, int m, double remaining, double zr, double zi, double tol,
                        uint32_t lane) {
     double tn = 0.0;
     if (static_cast<int>(lane) < k) tn = fmax(fabs(sh.al[lane]), lane > 0 ? sh.bt[lane] : 0.0);
@@ -474,7 +506,7 @@ __device__ void decide(Shared<NT> &sh, int k, int m, double remaining, double zr
 // v <- e^{z H_blk} v (in place), Lanczos with restarts and the step control of the
 // single-vector path
 template <int NT, int CHB, int L>
-__device__ void prop(Ctx<NT, CHB> &c, int blk, double zr, double zi, float2 *v) {
+__device__ void prop(Ctx<NT, CHB> &c, int blk, double zr, double zi, gf2 *v) {
     constexpr int R = (1 << L) / NT;
     if (c.status) return;
     double nrm = sqrt(norm2<NT, CHB, L>(c, v));
@@ -522,12 +554,12 @@ __device__ void prop(Ctx<NT, CHB> &c, int blk, double zr, double zi, float2 *v) 
         for (int r = 0; r < R; ++r) {
             double sr = 0.0, si = 0.0;
             for (int i = 0; i < k; ++i) {
-                const float2 q = c.basis[static_cast<size_t>(i) * c.p.vec_stride + r * NT + c.tid];
+                const float2 q = ld(c.basis + (static_cast<size_t>(i) * c.p.vec_stride + r * NT + c.tid));
                 const double cr = c.sh.cre[i], ci = c.sh.cim[i];
                 sr += cr * q.x - ci * q.y;
                 si += cr * q.y + ci * q.x;
             }
-            v[r * NT + c.tid] = float2{static_cast<float>(nrm * sr), static_cast<float>(nrm * si)};
+            st(v + (r * NT + c.tid), float2{static_cast<float>(nrm * sr), static_cast<float>(nrm * si)});
         }
         __syncthreads();
         remaining -= tau;
@@ -546,7 +578,7 @@ template <int NT, int CHB, int L>
 __device__ __attribute__((noinline)) void run_job(Ctx<NT, CHB> &c, double2 *F) {
     const BatchJob &jb = c.job;
     const double beta = jb.beta;
-    float2 *l = c.vec[0], *r2 = c.vec[1], *r4 = c.vec[2], *tmp = c.vec[3];
+    gf2 *l = c.vec[0], *r2 = c.vec[1], *r4 = c.vec[2], *tmp = c.vec[3];
     for (int A = 0; A < 2; ++A) {
         const int B = 1 - A;
         haar<NT, CHB, L>(c, A, l);
@@ -588,7 +620,7 @@ __global__ void __launch_bounds__(NT, OCC * NT / 256) otoc_batch_kernel(BatchPar
     __shared__ BatchTerm tl[2][TL];
     const uint32_t tid = threadIdx.x;
     for (int j = tid; j < 4 * kCheb; j += NT) sh.cosb[j] = cos(M_PI * j / (2.0 * kCheb));
-    float2 *slot = p.ws + static_cast<size_t>(blockIdx.x) * p.slot_stride;
+    gf2 *slot = (gf2 *)(p.ws + static_cast<size_t>(blockIdx.x) * p.slot_stride);   // address-space cast
     for (;;) {
         __syncthreads();
         if (tid == 0) job_sh = static_cast<int>(atomicAdd(p.counter, 1u));
@@ -599,7 +631,7 @@ __global__ void __launch_bounds__(NT, OCC * NT / 256) otoc_batch_kernel(BatchPar
         double2 *F = reinterpret_cast<double2 *>(p.F) + static_cast<size_t>(ji) * p.nt;
         if (tid == 0)
             for (int k = 0; k < p.nt; ++k) F[k] = double2{0.0, 0.0};
-        Ctx<NT, CHB> c{p, sh, buf, jb, slot, {slot + static_cast<size_t>(p.m + 1) * p.vec_stride,
+        Ctx<NT, CHB> c{p, *(LShared<NT> *)(&sh), (lf2 *)(buf), jb, slot, {slot + static_cast<size_t>(p.m + 1) * p.vec_stride,
                                                slot + static_cast<size_t>(p.m + 2) * p.vec_stride,
                                                slot + static_cast<size_t>(p.m + 3) * p.vec_stride,
                                                slot + static_cast<size_t>(p.m + 4) * p.vec_stride},
@@ -608,8 +640,8 @@ __global__ void __launch_bounds__(NT, OCC * NT / 256) otoc_batch_kernel(BatchPar
             for (int blk = 0; blk < 2; ++blk)
                 for (int t = static_cast<int>(tid); t < jb.K; t += NT) tl[blk][t] = p.terms[jb.term_off[blk] + t];
             __syncthreads();
-            c.lterms[0] = tl[0];
-            c.lterms[1] = tl[1];
+            c.lterms[0] = (lterm *)(tl[0]);
+            c.lterms[1] = (lterm *)(tl[1]);
         }
         // the block size is a compile-time parameter of the job code
         switch (jb.L) {
