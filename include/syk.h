@@ -57,7 +57,10 @@ typedef enum {
     SYK_ENSEMBLE_EXACT_K = 0,   /* exactly K = round(k N) distinct 4-subsets, uniform */
     SYK_ENSEMBLE_BERNOULLI = 1  /* every 4-subset kept with probability p = k N / C(N,4) */
 } syk_ensemble;
-typedef enum { SYK_BLOCK_U = 0, SYK_BLOCK_D = 1 } syk_block;
+/* Parity sector of a state vector: the U block (even parity of the most significant qubit,
+ * 2^L amplitudes), the D block, or the full 2^(L+1)-amplitude space (U block first, then D;
+ * H is block diagonal in parity, so it acts on the two halves separately). */
+typedef enum { SYK_BLOCK_U = 0, SYK_BLOCK_D = 1, SYK_FULL = 2 } syk_block;
 
 typedef struct {
     int N, L, K;           /* Majoranas, block qubits, number of terms */
@@ -111,8 +114,10 @@ syk_status syk_get_terms(const syk_ham *h, size_t cap, int32_t *ijkl, double *J,
  * y = H_blk x, matrix-free (supplement Sec. I.A, Algorithm 1): for every m < 2^L,
  * y[m] = sum_a (J_a/4) i^{p_a} (-1)^{popcount((m ^ x_a) & z_a)} x[m ^ x_a].
  * x, y: device, `nvec` vectors, vector v at element offset v*ld, n_amps = 2^L complex
- * elements each, ld >= n_amps.  x and y must not overlap.  y is overwritten.
- * Errors: EINVAL (n_amps != 2^L, nvec < 1, ld < n_amps, null), EDEVICE. */
+ * elements each (2^(L+1) for SYK_FULL: H_UU on the first half, H_DD on the second), ld >=
+ * n_amps.  x and y must not overlap.  y is overwritten.
+ * Errors: EINVAL (n_amps not the sector size, nvec < 1, ld < n_amps, null), EUNSUPPORTED
+ * (SYK_FULL on an operator handle of syk_op_to_hamiltonian), EDEVICE. */
 syk_status syk_apply_H(const syk_ham *h, syk_block blk, syk_dtype dt, const void *x, void *y,
                        uint64_t n_amps, int nvec, uint64_t ld, void *stream);
 
@@ -166,6 +171,9 @@ void syk_krylov_default_opts(syk_dtype dt, syk_krylov_opts *o);
  * meets the tolerance for the remaining tau, else the largest tau that meets it is taken
  * and the propagation restarts from the result.  beta_j ~ 0 is an invariant subspace
  * (exact result).  v, out: device, n_amps = 2^L; out == v allowed.  stats may be NULL.
+ * SYK_FULL (n_amps = 2^(L+1)): the two halves are propagated separately (e^{zH} is block
+ * diagonal), each to the tolerance relative to its own norm; the statistics are summed
+ * (breakdown: either half).
  * Uses a library-owned device workspace of (m + 2) vectors, reused across calls.
  * Errors: EINVAL, ENOMEM, EDEVICE, ENOTCONV (max_substeps exceeded), ENUMERIC. */
 syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double z_re, double z_im,

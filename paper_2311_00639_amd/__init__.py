@@ -23,6 +23,7 @@ from ._lib import (  # noqa: F401
     Engine,
     BLOCK_U,
     BLOCK_D,
+    FULL,
     SykError,
     Hamiltonian,
     Operator,

@@ -9,7 +9,7 @@ _LIBPATH = os.path.join(_HERE, "libsyk.so")
 
 C64, C128 = 0, 1
 EXACT_K, BERNOULLI = 0, 1
-BLOCK_U, BLOCK_D = 0, 1
+BLOCK_U, BLOCK_D, FULL = 0, 1, 2
 
 STATUS = {0: "SYK_OK", 1: "SYK_EINVAL", 2: "SYK_EUNSUPPORTED", 3: "SYK_ENOMEM", 4: "SYK_EDEVICE",
           5: "SYK_ENOTCONV", 6: "SYK_ENUMERIC", 7: "SYK_ECANCELLED", 8: "SYK_EAGAIN"}
@@ -261,10 +261,11 @@ def create_hamiltonian(N: int, q: int, k: float, seed: int, ensemble: int = EXAC
 
 
 def apply_H(ham: Hamiltonian, block: int, x, y, nvec: int = 1, ld: int = None, stream=None):
-    """y = H_block x for torch tensors x, y of complex dtype on the GPU.
+    """y = H_block x for torch tensors x, y of complex dtype on the GPU (block FULL: the whole
+    2^(N/2) space, U block then D block).
 
     With nvec > 1 the tensors hold nvec vectors of leading dimension ld (elements)."""
-    n = 1 << ham.info()["L"]
+    n = (2 if block == FULL else 1) << ham.info()["L"]
     ld = n if ld is None else ld
     _check(_lib.syk_apply_H(ham.handle, block, _dtype_of(x), _ptr(x), _ptr(y), n, nvec, ld, _stream(stream)))
 
@@ -301,7 +302,7 @@ def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None,
         o.max_substeps = max_substeps
     st = KrylovStats()
     z = complex(z)
-    n = 1 << ham.info()["L"]
+    n = (2 if block == FULL else 1) << ham.info()["L"]
     _check(_lib.syk_krylov_expm(ham.handle, block, dt, z.real, z.imag, _ptr(v), _ptr(out), n, ct.byref(o),
                                 ct.byref(st), _stream(stream)))
     return {f: getattr(st, f) for f, _ in KrylovStats._fields_}

@@ -248,19 +248,29 @@ syk_status syk_apply_H(const syk_ham *h, syk_block blk, syk_dtype dt, const void
                        int nvec, uint64_t ld, void *stream) {
     return guarded([&] {
         require(h && x && y, "NULL argument");
-        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
+        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D || blk == SYK_FULL, "invalid block");
         require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
-        require(n_amps == block_amps(h->h.N), "n_amps must equal 2^(N/2-1)");
+        const uint64_t nb = block_amps(h->h.N);
+        require(n_amps == (blk == SYK_FULL ? 2 * nb : nb), "n_amps must equal 2^(N/2-1) (2^(N/2) for SYK_FULL)");
         require(nvec >= 1 && nvec <= 65535, "nvec must lie in [1, 65535]");
         require(ld >= n_amps, "ld must be >= n_amps");
+        if (blk == SYK_FULL && h->h.ensemble < 0)
+            syk::fail(SYK_EUNSUPPORTED, "an operator handle has no parity sectors");
         check_device();
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
-        if (dt == SYK_C64)
-            syk::apply_block<float>(H, blk, 0, static_cast<const float *>(x), static_cast<float *>(y), nvec, ld,
-                                    as_stream(stream));
-        else
-            syk::apply_block<double>(H, blk, 0, static_cast<const double *>(x), static_cast<double *>(y), nvec, ld,
-                                     as_stream(stream));
+        // the full space is the U block followed by the D block
+        const int b0 = blk == SYK_FULL ? SYK_BLOCK_U : blk, b1 = blk == SYK_FULL ? SYK_BLOCK_D : -1;
+        if (dt == SYK_C64) {
+            const float *xf = static_cast<const float *>(x);
+            float *yf = static_cast<float *>(y);
+            syk::apply_block<float>(H, b0, 0, xf, yf, nvec, ld, as_stream(stream));
+            if (b1 >= 0) syk::apply_block<float>(H, b1, 0, xf + 2 * nb, yf + 2 * nb, nvec, ld, as_stream(stream));
+        } else {
+            const double *xd = static_cast<const double *>(x);
+            double *yd = static_cast<double *>(y);
+            syk::apply_block<double>(H, b0, 0, xd, yd, nvec, ld, as_stream(stream));
+            if (b1 >= 0) syk::apply_block<double>(H, b1, 0, xd + 2 * nb, yd + 2 * nb, nvec, ld, as_stream(stream));
+        }
     });
 }
 
@@ -334,10 +344,13 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
     return guarded([&] {
         if (h && !h->h.hermitian) syk::fail(SYK_EUNSUPPORTED, "Lanczos propagation needs a Hermitian operator");
         require(h && v && out && o, "NULL argument");
-        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
+        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D || blk == SYK_FULL, "invalid block");
         require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
-        require(n_amps == block_amps(h->h.N), "n_amps must equal 2^(N/2-1)");
+        const uint64_t nb = block_amps(h->h.N);
+        require(n_amps == (blk == SYK_FULL ? 2 * nb : nb), "n_amps must equal 2^(N/2-1) (2^(N/2) for SYK_FULL)");
         require(std::isfinite(z_re) && std::isfinite(z_im), "z must be finite");
+        if (blk == SYK_FULL && h->h.ensemble < 0)
+            syk::fail(SYK_EUNSUPPORTED, "an operator handle has no parity sectors");
         syk::check_krylov_opts(*o);
         check_device();
         auto &H = const_cast<syk::Hamiltonian &>(h->h);
@@ -345,14 +358,25 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
         auto &ws = syk::thread_workspace(0);
         hipStream_t s = as_stream(stream);
         const std::complex<double> z(z_re, z_im);
-        if (dt == SYK_C64) {
-            ws.ensure(syk::krylov_workspace_bytes(n_amps, o->m, sizeof(float)));
-            syk::KrylovRun<float> kr(H, blk, 0, n_amps, o->m, ws.ptr(), s);
-            kr.run(z, static_cast<const float *>(v), static_cast<float *>(out), *o, st);
-        } else {
-            ws.ensure(syk::krylov_workspace_bytes(n_amps, o->m, sizeof(double)));
-            syk::KrylovRun<double> kr(H, blk, 0, n_amps, o->m, ws.ptr(), s);
-            kr.run(z, static_cast<const double *>(v), static_cast<double *>(out), *o, st);
+        // one block, or both halves of the full space (U first), each its own Lanczos run
+        const int nblk = blk == SYK_FULL ? 2 : 1;
+        for (int q = 0; q < nblk; ++q) {
+            const int b = blk == SYK_FULL ? q : blk;
+            const uint64_t off = static_cast<uint64_t>(q) * 2 * nb;   // in scalars
+            syk_krylov_stats sq{};
+            if (dt == SYK_C64) {
+                ws.ensure(syk::krylov_workspace_bytes(nb, o->m, sizeof(float)));
+                syk::KrylovRun<float> kr(H, b, 0, nb, o->m, ws.ptr(), s);
+                kr.run(z, static_cast<const float *>(v) + off, static_cast<float *>(out) + off, *o, sq);
+            } else {
+                ws.ensure(syk::krylov_workspace_bytes(nb, o->m, sizeof(double)));
+                syk::KrylovRun<double> kr(H, b, 0, nb, o->m, ws.ptr(), s);
+                kr.run(z, static_cast<const double *>(v) + off, static_cast<double *>(out) + off, *o, sq);
+            }
+            st.substeps += sq.substeps;
+            st.matvecs += sq.matvecs;
+            st.breakdown |= sq.breakdown;
+            st.err_est += sq.err_est;
         }
         SYK_HIP(hipStreamSynchronize(s));
         if (stats) *stats = st;

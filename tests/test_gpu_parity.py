@@ -497,3 +497,43 @@ def test_otoc_rejects_bad_arguments():
         with pytest.raises(syk.SykError) as e:
             syk.otoc(h, *args, dtype=syk.C128)
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_full_sector_apply_and_propagator_vs_dense(dt):
+    """SYK_FULL: the whole 2^(N/2) space (U block, then D) against the oracle's full dense H
+    (N = 12): y = H x, and e^{zH} v for a complex z."""
+    N, k, seed = 12, 4, 21
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    H = dense.hamiltonian(N, subs, J)
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    d = H.shape[0]
+    x = inputs.complex_vector(d, 61)[0]
+    xd = dev(x, cdt(dt))
+    yd = torch.empty_like(xd)
+    syk.apply_H(h, syk.FULL, xd, yd)
+    ref = H @ host(xd)
+    assert rel(host(yd), ref) <= (1e-13 if dt == syk.C128 else 2e-7)
+    z = -0.3 - 1.7j
+    out = torch.empty_like(xd)
+    st = syk.krylov_expm(h, syk.FULL, z, xd, out, m=30)
+    w, U = np.linalg.eigh(H)
+    ref = U @ (np.exp(z * w) * (U.conj().T @ host(xd)))
+    assert rel(host(out), ref) <= (1e-10 if dt == syk.C128 else 1e-5)
+    assert st["matvecs"] >= 2
+
+
+def test_full_sector_is_the_two_blocks_N40():
+    """SYK_FULL at a tiled size (N = 40) equals the U and D applies on the two halves, bitwise."""
+    h = syk.create_hamiltonian(40, 4, 4, 77)
+    n = 1 << 19
+    g = torch.Generator(device="cuda").manual_seed(77)
+    x = torch.randn(2 * n, dtype=torch.complex64, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    syk.apply_H(h, syk.FULL, x, y)
+    yu = torch.empty(n, dtype=torch.complex64, device="cuda")
+    yv = torch.empty_like(yu)
+    syk.apply_H(h, syk.BLOCK_U, x[:n].contiguous(), yu)
+    syk.apply_H(h, syk.BLOCK_D, x[n:].contiguous(), yv)
+    torch.cuda.synchronize()
+    assert torch.equal(y[:n], yu) and torch.equal(y[n:], yv)

@@ -320,3 +320,17 @@ def test_otoc_ensemble_argument_checks_without_gpu():
     assert e.value.status == 2
     with pytest.raises(syk.SykError):
         syk.otoc_ensemble(24, 4, 1, 2, 23, 22, 1.0, ts, ensemble=7)
+
+
+def test_full_sector_argument_checks_without_gpu():
+    """SYK_FULL takes 2^(N/2) amplitudes and is refused for operator handles, before any
+    device work."""
+    import ctypes as ct
+    from paper_2311_00639_amd import _lib
+    h = syk.create_hamiltonian(12, 4, 3, 1)
+    n = 1 << 5
+    st = _lib._lib.syk_apply_H(h.handle, syk.FULL, syk.C64, ct.c_void_p(1), ct.c_void_p(2), n, 1, n, None)
+    assert st == 1                                                   # EINVAL: 2^L is not the full size
+    op = syk.Operator(4, [1], [0], [1.0]).to_hamiltonian()
+    st = _lib._lib.syk_apply_H(op.handle, syk.FULL, syk.C64, ct.c_void_p(1), ct.c_void_p(2), 1 << 5, 1, 1 << 5, None)
+    assert st == 2                                                   # EUNSUPPORTED
