@@ -537,3 +537,44 @@ def test_full_sector_is_the_two_blocks_N40():
     syk.apply_H(h, syk.BLOCK_D, x[n:].contiguous(), yv)
     torch.cuda.synchronize()
     assert torch.equal(y[:n], yu) and torch.equal(y[n:], yv)
+
+
+def test_handle_shared_by_threads_on_streams():
+    """One handle used at once from four host threads, each on its own stream (plans are
+    built concurrently on first use): apply_H and krylov_expm give the results of the same
+    calls made one after another, bitwise."""
+    import threading
+    N = 44
+    h = syk.create_hamiltonian(N, 4, 4, 404)
+    n = 1 << (N // 2 - 1)
+    xs = [dev(inputs.complex_vector(n, 800 + i)[0], torch.complex64) for i in range(4)]
+    outs = [[None, None] for _ in range(4)]
+    errors = []
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                y = torch.empty_like(xs[i])
+                syk.apply_H(h, i % 2, xs[i], y, stream=s)
+                e = torch.empty_like(xs[i])
+                syk.krylov_expm(h, i % 2, -0.5j, xs[i], e, m=20, stream=s)
+            s.synchronize()
+            outs[i] = [y, e]
+        except Exception as ex:          # reported by the main thread
+            errors.append(ex)
+
+    threads = [threading.Thread(target=work, args=(i,)) for i in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    torch.cuda.synchronize()
+    for i in range(4):
+        y = torch.empty_like(xs[i])
+        syk.apply_H(h, i % 2, xs[i], y)
+        e = torch.empty_like(xs[i])
+        syk.krylov_expm(h, i % 2, -0.5j, xs[i], e, m=20)
+        torch.cuda.synchronize()
+        assert torch.equal(outs[i][0], y) and torch.equal(outs[i][1], e)
