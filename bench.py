@@ -37,6 +37,9 @@ Also reported, outside the timed region:
   event-timed launch), and the algorithmic HBM fraction of a whole Lanczos iteration (7
   vector passes: x read, y written and v_{j-1}, v_j read by the fused epilogue, then y,
   u_j read and u_{j+1} written by the residual pass);
+* lyapunov_pipeline: disorder averages at N = 14, 22, 30 (128 realisations each, beta = 5,
+  k = 4), crossing times at F0 = 0.75 and 0.85 and the Eq. (5) / Eq. (6) fits: the analysis
+  pipeline end to end and its cost, not a Table I estimate;
 * cpu_baseline.plain_cpu_lanczos: a plain C/OpenMP complex128 matrix-free Lanczos
   iteration on the same block (oracle/cpu_lanczos.c), projected to realisations/hour;
 * mixed_precision also times the complex64 path on the same four points, giving the
@@ -180,6 +183,41 @@ def cpu_lanczos_leg(matvecs_per_realisation: float, steps: int = 1):
             "sample": f"{steps} Lanczos iterations on the N=56 K=224 U block in complex128 (plain C, OpenMP, "
                       f"no tiling), projected by {matvecs_per_realisation:.0f} matvecs per realisation "
                       f"measured on the GPU"}
+
+
+def lyapunov_leg(syk, n_real=128, beta=5.0, k=4.0):
+    """The t*(N) / lambda_L pipeline end to end on a small ensemble: disorder-averaged
+    normalised OTOCs at N = 14, 22, 30 (batched path where it serves, else single-request),
+    crossing times at F0 = 0.75 and 0.85, and the fits of Eq. (5) (slope pairs N, N + 8) and
+    Eq. (6).  A demonstration of the pipeline and its cost, not a Table I estimate (that needs
+    ~10^4 realisations per point and N up to 54)."""
+    ts = [0.1 * n for n in range(81)]
+    Ns = (14, 22, 30)
+    t0 = time.perf_counter()
+    curves, paths = {}, {}
+    for n_maj in Ns:
+        mean, sem, st = syk.otoc_ensemble(n_maj, k, 20000 + 1000 * n_maj, n_real, n_maj - 1, n_maj - 2, beta, ts,
+                                          nvec=1, state_seed=30000 + 1000 * n_maj, dtype=syk.C64, m=30, tol=1e-7)
+        curves[n_maj] = (mean, sem)
+        paths[n_maj] = "batched" if st["path"] == 0 else "single-request"
+    wall = time.perf_counter() - t0
+    out = {"N": list(Ns), "realisations_per_N": n_real, "beta": beta, "k": k, "t_grid": "0:0.1:8", "paths": paths,
+           "wall_s": wall, "realisations_per_h": 3600.0 * n_real * len(Ns) / wall, "F0": {}}
+    for F0 in (0.75, 0.85):
+        tst, ter = [], []
+        for n_maj in Ns:
+            a, b = syk.crossing_time(ts, curves[n_maj][0], F0, curves[n_maj][1])
+            tst.append(a)
+            ter.append(b)
+        rec = {"tstar": tst, "tstar_err": ter}
+        if all(x == x for x in tst):                     # every curve crossed F0
+            sl = syk.lyapunov_fit(Ns, tst, ter, method=syk.FIT_SLOPE, terms=0)
+            gl = syk.lyapunov_fit(Ns, tst, ter, method=syk.FIT_GLOBAL, terms=0)
+            rec["lambda_slope_eq5"] = [sl["lambda"], sl["lambda_err"]]
+            rec["inverse_slopes"] = [list(map(float, sl["points"][0])), list(map(float, sl["points"][1]))]
+            rec["lambda_global_eq6"] = [gl["lambda"], gl["lambda_err"]]
+        out["F0"][str(F0)] = rec
+    return out
 
 
 def batched_leg(syk, n_real=512, seed=3000):
@@ -375,6 +413,9 @@ def main():
     if not args.no_batched:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         rec["batched"] = batched_leg(syk)
+    if not args.no_batched:
+        print("[bench] t*(N) and lambda_L pipeline", file=sys.stderr, flush=True)
+        rec["lyapunov_pipeline"] = lyapunov_leg(syk)
     if not args.no_serving:
         print("[bench] serving leg", file=sys.stderr, flush=True)
         rec["serving"] = serving_leg(syk)
