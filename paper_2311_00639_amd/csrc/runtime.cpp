@@ -68,7 +68,8 @@ const std::vector<TiledVariant> &tiled_variants<float>() {
     static const std::vector<TiledVariant> v = {{13, 3, 2, 1, 1, 0, 0}, {13, 3, 1, 0, 2, 0, 0}, {12, 3, 2, 1, 2, 0, 0},
                                                 {12, 2, 4, 3, 1, 0, 0}, {13, 3, 2, 1, 1, 1, 0}, {13, 3, 2, 1, 1, 0, 1},
                                                 {13, 3, 2, 1, 1, 0, 2}, {12, 3, 2, 1, 2, 0, 1}, {13, 3, 2, 1, 1, 2, 0},
-                                                {13, 3, 2, 1, 1, 2, 1}, {13, 3, 2, 1, 1, 2, 2}};
+                                                {13, 3, 2, 1, 1, 2, 1}, {13, 3, 2, 1, 1, 2, 2}, {11, 2, 2, 1, 2, 2, 0},
+                                                {10, 2, 2, 1, 4, 2, 0}, {11, 2, 2, 1, 2, 2, 1}};
     return v;
 }
 template <>
@@ -76,7 +77,8 @@ const std::vector<TiledVariant> &tiled_variants<double>() {
     static const std::vector<TiledVariant> v = {{12, 2, 2, 1, 1, 0, 0}, {12, 2, 1, 0, 2, 0, 0}, {11, 2, 2, 1, 2, 0, 0},
                                                 {11, 1, 4, 3, 1, 0, 0}, {12, 2, 2, 1, 1, 1, 0}, {12, 2, 2, 1, 1, 0, 1},
                                                 {12, 2, 2, 1, 1, 0, 2}, {11, 2, 2, 1, 2, 0, 1}, {12, 2, 2, 1, 1, 2, 0},
-                                                {12, 2, 2, 1, 1, 2, 1}, {12, 2, 2, 1, 1, 2, 2}};
+                                                {12, 2, 2, 1, 1, 2, 1}, {12, 2, 2, 1, 1, 2, 2}, {11, 2, 2, 1, 2, 2, 0},
+                                                {10, 2, 2, 1, 4, 2, 0}, {11, 2, 2, 1, 2, 2, 1}};
     return v;
 }
 // Before (or without) autotuning: the first of a preference order (control-block records

@@ -151,7 +151,7 @@ def test_apply_h_tiled_smallest_sizes(N, dt, blk):
         assert np.all(np.abs(y - yref) <= K * U24 * mag)
 
 
-N_VARIANTS = 11
+N_VARIANTS = 14
 
 
 @pytest.mark.parametrize("dt", [syk.C128, syk.C64])

@@ -156,7 +156,7 @@ def test_plan_describe_every_variant_N56(dt):
     several tiles per workgroup streams fewer partner tiles per output tile."""
     h = syk.create_hamiltonian(56, 4, 4, 56)
     per_tile = {}
-    for v in range(11):
+    for v in range(14):
         syk.select_variant(h, dt, v)
         d = syk.plan_describe(h, 0, dt, -1)
         assert d["variant"] == v and d["tiled"] == 1
