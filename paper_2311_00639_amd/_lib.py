@@ -493,8 +493,8 @@ def autotune(ham: Hamiltonian, dtype: int, stream=None):
     """Time the tiled apply_H variants on this Hamiltonian.  Returns (chosen variant,
     per-variant ms per apply, -1 where skipped)."""
     v = ct.c_int(-1)
-    ms = (ct.c_float * 16)()
-    _check(_lib.syk_autotune(ham.handle, dtype, ct.byref(v), ms, 16, _stream(stream)))
+    ms = (ct.c_float * 64)()
+    _check(_lib.syk_autotune(ham.handle, dtype, ct.byref(v), ms, 64, _stream(stream)))
     return v.value, [round(float(t), 4) for t in ms if t != -1.0]
 
 

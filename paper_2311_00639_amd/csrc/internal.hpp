@@ -124,7 +124,7 @@ struct Hamiltonian {
     std::vector<DeviceTables> dev[2];  // indexed by device ordinal
     // plans keyed by (block, double?, device, rotation, variant)
     std::map<std::tuple<int, int, int, int, int>, ApplyPlan> plans;
-    int rotation[2][8] = {{-1, -1, -1, -1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1, -1, -1, -1}};
+    std::map<std::pair<int, int>, int> rotation;               // (double?, variant) -> planned rotation
     std::map<std::pair<int, int>, int> tuned;                   // (double?, device) -> variant
     const DeviceTables &tables(int blk);
     template <typename T>

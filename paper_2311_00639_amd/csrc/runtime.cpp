@@ -122,11 +122,13 @@ template <typename T>
 int Hamiltonian::internal_rotation(int variant) {
     if (!use_tiled<T>(L)) return 0;
     const int prec = sizeof(T) == 8 ? 1 : 0;
+    const TiledVariant &tv = tiled_variants<T>().at(variant);     // throws for an unknown variant
     std::lock_guard<std::mutex> g(dev_mu);
-    int &r = rotation[prec][variant];
-    const TiledVariant &tv = tiled_variants<T>().at(variant);
-    if (r < 0) r = choose_rotation(block_terms[0], L, tv.bt, resident_bits(tv), tv.w);
-    return r;
+    auto it = rotation.find({prec, variant});
+    if (it == rotation.end())
+        it = rotation.emplace(std::make_pair(prec, variant), choose_rotation(block_terms[0], L, tv.bt, resident_bits(tv),
+                                                                              tv.w)).first;
+    return it->second;
 }
 template int Hamiltonian::internal_rotation<float>(int);
 template int Hamiltonian::internal_rotation<double>(int);

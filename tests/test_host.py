@@ -334,3 +334,18 @@ def test_full_sector_argument_checks_without_gpu():
     op = syk.Operator(4, [1], [0], [1.0]).to_hamiltonian()
     st = _lib._lib.syk_apply_H(op.handle, syk.FULL, syk.C64, ct.c_void_p(1), ct.c_void_p(2), 1 << 5, 1, 1 << 5, None)
     assert st == 2                                                   # EUNSUPPORTED
+
+
+def test_planner_rotation_is_cached_per_precision_and_variant():
+    """The planner's layout is remembered per (precision, variant): planning every variant
+    in one precision first leaves the other precision's choices unchanged, and each equals
+    the choice a fresh handle makes for that variant alone."""
+    mixed = syk.create_hamiltonian(56, 4, 4, 57)
+    for first, second in [(syk.C128, syk.C64), (syk.C64, syk.C128)]:
+        for dt in (first, second):
+            for v in range(14):
+                syk.select_variant(mixed, dt, v)
+                got = syk.plan_describe(mixed, 0, dt, -1)["rot"]
+                fresh = syk.create_hamiltonian(56, 4, 4, 57)
+                syk.select_variant(fresh, dt, v)
+                assert got == syk.plan_describe(fresh, 0, dt, -1)["rot"], (dt, v)
