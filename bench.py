@@ -44,6 +44,9 @@ Also reported, outside the timed region:
   iteration on the same block (oracle/cpu_lanczos.c), projected to realisations/hour;
 * mixed_precision also times the complex64 path on the same four points, giving the
   speed ratio over the plain complex128 path at equal OTOC accuracy.
+* other_entry_points: the Green function of chi_55 on the benchmark realisation (beta = 10,
+  t = 0:0.25:5), one dense-SYK apply_H at N = 38 (K = 73815), and a transverse-field Ising
+  chain on 27 qubits as a general spin operator (one apply_H, one e^{-iH} propagation).
 
 --pmc-sample runs a short chain (one beta, t = 0, 0.25, 0.5) in the identical launch
 configuration plus a 1 GiB device copy, for hardware-counter passes.
@@ -217,6 +220,68 @@ def lyapunov_leg(syk, n_real=128, beta=5.0, k=4.0):
             rec["inverse_slopes"] = [list(map(float, sl["points"][0])), list(map(float, sl["points"][1]))]
             rec["lambda_global_eq6"] = [gl["lambda"], gl["lambda_err"]]
         out["F0"][str(F0)] = rec
+    return out
+
+
+def next_rows_leg(syk, h, stream):
+    """Costs of the other entry points on this GPU, outside the timed region:
+    * green: the Green function G_R(t) of chi_55 on the benchmark realisation (N = 56,
+      k = 4, beta = 10, t = 0:0.25:5, complex64, Krylov dim 60, tol 1e-6);
+    * dense: one apply_H of dense SYK (p = 1, K = C(38,4) = 73815) at N = 38, best
+      autotuned variant, with its VALU-floor fraction;
+    * spin_operator: a transverse-field Ising chain on 27 qubits (sum Z_q Z_{q+1} + 0.7 sum X_q)
+      through syk_op_to_hamiltonian: one apply_H (best variant) and one e^{-iH} propagation."""
+    import math
+
+    import torch
+    out = {}
+    ts = [0.25 * n for n in range(21)]
+    t0 = time.perf_counter()
+    raw, nrm, im, st = syk.green(h, N - 1, 10.0, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64, m=M_KRYLOV,
+                                 tol=TOL_C64, stream=stream)
+    wall = time.perf_counter() - t0
+    out["green"] = {"n": N - 1, "beta": 10.0, "t_grid": "0:0.25:5", "wall_s": wall, "matvecs": st["matvecs"],
+                    "ms_per_matvec": wall * 1e3 / max(st["matvecs"], 1),
+                    "G_norm": {str(ts[i]): float(nrm[i]) for i in (0, 4, 8, 20)}}
+    syk.release_workspace()
+
+    nd = 38
+    hd = syk.create_hamiltonian(nd, 4, math.comb(nd, 4) / nd, 2, syk.BERNOULLI)
+    info = hd.info()
+    variant, ms = syk.autotune(hd, syk.C64, stream=stream)
+    best = min(m for m in ms if m > 0)
+    ta = info["K"] * info["block_dim"]
+    out["dense"] = {"N": nd, "K": info["K"], "variant": variant, "ms": best, "term_amps_per_s": ta / (best * 1e-3),
+                    "valu_floor_frac": ta / 3.93e13 / (best * 1e-3), "variant_ms": ms}
+    hd.close()
+
+    L, g = 27, 0.7
+    xs, zs, cs = [], [], []
+    for q in range(L - 1):
+        xs.append(0), zs.append((1 << q) | (1 << (q + 1))), cs.append(1.0)
+    for q in range(L):
+        xs.append(1 << q), zs.append(0), cs.append(g)
+    op = syk.Operator(L, xs, zs, cs)
+    ho = op.to_hamiltonian()
+    variant, ms = syk.autotune(ho, syk.C64, stream=stream)
+    best = min(m for m in ms if m > 0)
+    v = torch.randn(1 << L, dtype=torch.complex64, device="cuda")
+    v /= torch.linalg.vector_norm(v)
+    w = torch.empty_like(v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kst = syk.krylov_expm(ho, 0, -1j, v, w, m=M_KRYLOV, tol=TOL_C64, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out["spin_operator"] = {"L": L, "terms": len(xs), "apply_variant": variant, "apply_ms": best,
+                            "apply_term_amps_per_s": len(xs) * (1 << L) / (best * 1e-3),
+                            "apply_algorithmic_hbm_frac": 2.0 * (1 << L) * 8 / (best * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                            "expm_wall_s": wall, "expm_stats": kst,
+                            "norm_after": float(torch.linalg.vector_norm(w))}
+    del v, w
+    ho.close()
+    op.close()
+    syk.release_workspace()
     return out
 
 
@@ -410,6 +475,9 @@ def main():
         print("[bench] apply_H at k = 1", file=sys.stderr, flush=True)
         rec["apply_k1"] = apply_k1_leg(syk, stream)
         syk.release_workspace()
+    if not args.no_precision:
+        print("[bench] Green function, dense apply, spin operator", file=sys.stderr, flush=True)
+        rec["other_entry_points"] = next_rows_leg(syk, h, stream)
     if not args.no_batched:
         print("[bench] batched leg", file=sys.stderr, flush=True)
         rec["batched"] = batched_leg(syk)
