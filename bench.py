@@ -3,7 +3,7 @@
 Workload (mixed precision at scale): N = 56 Majoranas (parity blocks of 2^27 amplitudes),
 q = 4, k = 4 (K = 224 terms), one disorder realisation (seed 56), complex64 state
 vectors with double Lanczos reductions and tridiagonal exponential, Krylov dimension 60,
-per-propagation tolerance 1e-6 (complex64 rounding, not the tolerance, sets the error of F;
+per-propagation tolerance 3e-6 (complex64 rounding, not the tolerance, sets the error of F;
 the mixed_precision leg reports it), one Haar state (state_seed 5600), W = chi_55, V = chi_54, beta in {5, 10, 20},
 t = 0, 0.25, ..., 20 (81 points).
 
@@ -63,7 +63,7 @@ sys.path.insert(0, ROOT)
 N, K_SPARSITY, SEED, STATE_SEED = 56, 4, 56, 5600
 BETAS = (10.0, 5.0, 20.0)
 M_KRYLOV = 60
-TOL_C64 = 1e-6
+TOL_C64 = 3e-6
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 
@@ -226,7 +226,7 @@ def lyapunov_leg(syk, n_real=128, beta=5.0, k=4.0):
 def next_rows_leg(syk, h, stream):
     """Costs of the other entry points on this GPU, outside the timed region:
     * green: the Green function G_R(t) of chi_55 on the benchmark realisation (N = 56,
-      k = 4, beta = 10, t = 0:0.25:5, complex64, Krylov dim 60, tol 1e-6);
+      k = 4, beta = 10, t = 0:0.25:5, complex64, Krylov dim 60, tol 3e-6);
     * dense: one apply_H of dense SYK (p = 1, K = C(38,4) = 73815) at N = 38, best
       autotuned variant, with its VALU-floor fraction;
     * spin_operator: a transverse-field Ising chain on 27 qubits (sum Z_q Z_{q+1} + 0.7 sum X_q)
@@ -447,7 +447,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "sparse SYK OTOC realisation: N=56, q=4, k=4 (K=224), complex64 states, "
-                               "double Lanczos reductions, Krylov dim 60, tol 1e-6, beta in {5,10,20}, t=0:0.25:20, "
+                               "double Lanczos reductions, Krylov dim 60, tol 3e-6, beta in {5,10,20}, t=0:0.25:20, "
                                "1 Haar state, W=chi_55, V=chi_54; one step = one beta curve",
                    "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "krylov_tol": TOL_C64, "betas": list(BETAS), "nt": len(ts),
                    "betas_timed": [b for b, _ in results], "parallelism": "single GPU"},
