@@ -349,3 +349,15 @@ def test_planner_rotation_is_cached_per_precision_and_variant():
                 fresh = syk.create_hamiltonian(56, 4, 4, 57)
                 syk.select_variant(fresh, dt, v)
                 assert got == syk.plan_describe(fresh, 0, dt, -1)["rot"], (dt, v)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more, it exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr and p.stdout == ""
