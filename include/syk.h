@@ -146,7 +146,11 @@ typedef struct {
     int m;             /* maximum Krylov dimension per sub-step, 2 <= m <= 128 */
     double tol;        /* accepted a-posteriori error per propagation, relative to ||v|| */
     int reorth;        /* 0: three-term recurrence only; 1: local (second pass against
-                          v_j, v_{j-1}); 2: full classical Gram-Schmidt */
+                          v_j, v_{j-1}); 2: full, classical Gram-Schmidt twice (CGS2)
+                          against every basis vector; 3: partial (Simon 1984): the loss
+                          of orthogonality is estimated from the alpha/beta recurrence and
+                          a full CGS2 pass runs only on the steps where the estimate
+                          exceeds sqrt(eps) of the vector precision (and the step after) */
     int max_substeps;  /* 0 = unlimited */
 } syk_krylov_opts;
 
@@ -155,6 +159,7 @@ typedef struct {
     int matvecs;       /* apply_H calls */
     int breakdown;     /* 1 if an invariant subspace ended a Lanczos run (exact) */
     double err_est;    /* sum over sub-steps of the accepted error estimates, relative */
+    int reorths;       /* Lanczos steps given a full reorthogonalisation (reorth 2 and 3) */
 } syk_krylov_stats;
 
 /* Fill `o` with defaults for dtype dt (m = 30, tol = 1e-12 for C128 / 1e-7 for C64,

@@ -41,7 +41,8 @@ class KrylovOpts(ct.Structure):
 
 
 class KrylovStats(ct.Structure):
-    _fields_ = [("substeps", ct.c_int), ("matvecs", ct.c_int), ("breakdown", ct.c_int), ("err_est", ct.c_double)]
+    _fields_ = [("substeps", ct.c_int), ("matvecs", ct.c_int), ("breakdown", ct.c_int), ("err_est", ct.c_double),
+                ("reorths", ct.c_int)]
 
 
 PROGRESS_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_int, ct.c_int)

@@ -377,6 +377,7 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
             st.matvecs += sq.matvecs;
             st.breakdown |= sq.breakdown;
             st.err_est += sq.err_est;
+            st.reorths += sq.reorths;
         }
         SYK_HIP(hipStreamSynchronize(s));
         if (stats) *stats = st;

@@ -146,7 +146,7 @@ void check_krylov_opts(const syk_krylov_opts &o) {
     };
     require(o.m >= 2 && o.m <= 128, "Krylov m must lie in [2, 128]");
     require(o.tol > 0.0 && std::isfinite(o.tol), "Krylov tol must be positive");
-    require(o.reorth >= 0 && o.reorth <= 2, "reorth must be 0, 1 or 2");
+    require(o.reorth >= 0 && o.reorth <= 3, "reorth must be 0, 1, 2 or 3");
     require(o.max_substeps >= 0, "max_substeps must be >= 0");
 }
 
@@ -191,7 +191,7 @@ double KrylovRun<T>::norm(const T *v) {
 
 // one Lanczos iteration j: fills slot j+1, alpha[j], beta2[j+1]
 template <typename T>
-void KrylovRun<T>::iterate(int j, int reorth) {
+bool KrylovRun<T>::iterate(int j, int reorth) {
     T *vj = vec(j);
     T *w = vec(j + 1);
     if (reorth == 0 && use_tiled<T>(h_.L)) {
@@ -212,7 +212,7 @@ void KrylovRun<T>::iterate(int j, int reorth) {
         launch_lanczos_residual<T>(w, vj, alpha_ + 2 * j, beta2_, j, n_, partials_, s_);
         launch_reduce_partials(partials_, n_part_, 1, beta2_ + j + 1, s_);
         unnormalised_ = true;
-        return;
+        return false;
     }
     if (timer_) timer_->begin(s_);
     apply_block<T>(h_, blk_, rot_, vj, w, 1, n_, s_);
@@ -220,16 +220,83 @@ void KrylovRun<T>::iterate(int j, int reorth) {
     launch_lanczos_orth1<T>(w, j > 0 ? vec(j - 1) : nullptr, vj, beta2_ + j, n_, partials_, n_part_, s_);
     launch_reduce_partials(partials_, n_part_, 2, alpha_ + 2 * j, s_);
     launch_lanczos_orth2<T>(w, vj, alpha_ + 2 * j, n_, partials_, n_part_, s_);
-    if (reorth > 0) {
+    // reorth 1: one more pass against v_{j-1}, v_j; reorth 2: two full classical
+    // Gram-Schmidt passes against v_0 .. v_j; reorth 3: the same two passes on the steps
+    // where the estimated loss of orthogonality calls for them
+    bool full = reorth == 2;
+    if (reorth == 3) {
+        launch_reduce_partials(partials_, n_part_, 1, beta2_ + j + 1, s_);
+        full = partial_estimate(j);
+    }
+    if (reorth == 1 || full) {
         const int first = (reorth == 1) ? std::max(0, j - 1) : 0;
         const int nb = j + 1 - first;
-        launch_multi_dot_partials<T>(vec(first), vec_stride_, nb, w, n_, partials_, n_part_, s_);
-        launch_reduce_partials(partials_, n_part_, 2 * nb, scratch_, s_);
-        launch_subtract_proj<T>(w, vec(first), vec_stride_, nb, scratch_, n_, s_);
+        for (int pass = 0; pass < (full ? 2 : 1); ++pass) {
+            launch_multi_dot_partials<T>(vec(first), vec_stride_, nb, w, n_, partials_, n_part_, s_);
+            launch_reduce_partials(partials_, n_part_, 2 * nb, scratch_, s_);
+            launch_subtract_proj<T>(w, vec(first), vec_stride_, nb, scratch_, n_, s_);
+        }
         launch_norm2_partials<T>(w, n_, partials_, n_part_, s_);
     }
     launch_reduce_partials(partials_, n_part_, 1, beta2_ + j + 1, s_);
     launch_lanczos_normalize<T>(w, beta2_ + j + 1, n_, s_);
+    return full;
+}
+
+// Partial reorthogonalisation (H. D. Simon, Math. Comp. 42 (1984) 115-142).  With
+// normalised Lanczos vectors and beta_j v_{j+1} = H v_j - alpha_j v_j - beta_{j-1} v_{j-1},
+// omega_{j,k} = <v_j, v_k> obeys
+//   beta_j omega_{j+1,k} = beta_k omega_{j,k+1} + (alpha_k - alpha_j) omega_{j,k}
+//                          + beta_{k-1} omega_{j,k-1} - beta_{j-1} omega_{j-1,k}
+// up to rounding, which is modelled by adding 2 eps ||T|| with the sign of the sum
+// (omega_{j,j} = 1, omega_{j+1,j} = eps).  When max_k |omega_{j+1,k}| exceeds sqrt(eps),
+// v_{j+1} is reorthogonalised against every earlier vector, and so is v_{j+2} (the loss
+// of v_{j+1} also reaches the next vector through the recurrence); the estimates of a
+// reorthogonalised vector are reset to eps.  eps is the unit roundoff of the vectors.
+template <typename T>
+bool KrylovRun<T>::partial_estimate(int j) {
+    const double eps = sizeof(T) == 4 ? 5.9604644775390625e-8 : 1.1102230246251565e-16;
+    ha_.resize(static_cast<size_t>(m_) + 1);
+    hb_.resize(static_cast<size_t>(m_) + 2);
+    double ab[2];
+    std::vector<double> b2(static_cast<size_t>(j) + 2);
+    SYK_HIP(hipMemcpyAsync(ab, alpha_ + 2 * j, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+    SYK_HIP(hipMemcpyAsync(b2.data(), beta2_, (j + 2) * sizeof(double), hipMemcpyDeviceToHost, s_));
+    SYK_HIP(hipStreamSynchronize(s_));
+    ha_[j] = ab[0];
+    for (int k = 0; k <= j; ++k) hb_[k] = std::sqrt(b2[k + 1]);   // beta_k = ||w_k||
+    if (!std::isfinite(ha_[j]) || !std::isfinite(hb_[j])) fail(SYK_ENUMERIC, "non-finite Lanczos scalars");
+    if (j == 0) {
+        omega_[0].assign(static_cast<size_t>(m_) + 2, 0.0);
+        omega_[1].assign(static_cast<size_t>(m_) + 2, 0.0);
+        omega_[1][0] = 1.0;                  // row 0: <v_0, v_0>
+        anorm_ = 0.0;
+        force_next_ = false;
+    }
+    anorm_ = std::max({anorm_, std::fabs(ha_[j]), hb_[j]});
+    const double bj = hb_[j];
+    std::vector<double> next(static_cast<size_t>(m_) + 2, 0.0);
+    double worst = 0.0;
+    if (bj > 0.0) {
+        const std::vector<double> &cur = omega_[1], &prev = omega_[0];
+        for (int k = 0; k < j; ++k) {
+            double t = hb_[k] * cur[k + 1] + (ha_[k] - ha_[j]) * cur[k];
+            if (k > 0) t += hb_[k - 1] * cur[k - 1];
+            if (j > 0) t -= hb_[j - 1] * prev[k];
+            t += std::copysign(2.0 * eps * anorm_, t);
+            next[k] = t / bj;
+            worst = std::max(worst, std::fabs(next[k]));
+        }
+    }
+    next[j] = eps;
+    next[j + 1] = 1.0;
+    const bool due = force_next_ || worst > std::sqrt(eps);
+    force_next_ = due && !force_next_;
+    if (due)
+        for (int k = 0; k <= j; ++k) next[k] = eps;
+    omega_[0].swap(omega_[1]);
+    omega_[1].swap(next);
+    return due;
 }
 
 template <typename T>
@@ -256,7 +323,7 @@ void KrylovRun<T>::run(std::complex<double> z, const T *v, T *out, const syk_kry
         bool done = false;
         int next_check = every ? 1 : 4;
         for (int j = 0; j < m_ && !done; ++j) {
-            iterate(j, o.reorth);
+            if (iterate(j, o.reorth)) st.reorths += 1;
             k = j + 1;
             st.matvecs += 1;
             if (k < next_check && k < m_) continue;

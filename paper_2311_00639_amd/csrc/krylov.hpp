@@ -61,7 +61,11 @@ class KrylovRun {
 
   private:
     T *vec(int j) { return basis_ + static_cast<size_t>(j) * vec_stride_ * 2; }
-    void iterate(int j, int reorth);
+    // one Lanczos step; returns true if w was fully reorthogonalised
+    bool iterate(int j, int reorth);
+    // reorth = 3: update the estimates of |<v_{j+1}, v_k>| from alpha, beta; true if a
+    // full reorthogonalisation is due
+    bool partial_estimate(int j);
 
     Hamiltonian &h_;
     int blk_, rot_;
@@ -73,6 +77,12 @@ class KrylovRun {
     double *partials_ = nullptr, *alpha_ = nullptr, *beta2_ = nullptr, *coef_ = nullptr, *scratch_ = nullptr;
     double *fused_ = nullptr;
     bool unnormalised_ = false;   // fused path: basis slots >= 1 hold u_i = beta_{i-1} v_i
+    // partial reorthogonalisation state: omega_[0] row j - 1, omega_[1] row j of the
+    // estimated <v_j, v_k>; host copies of alpha and beta; whether the next step must be
+    // reorthogonalised too
+    std::vector<double> omega_[2], ha_, hb_;
+    double anorm_ = 0.0;
+    bool force_next_ = false;
     int n_part_ = 0;
     ApplyTimer *timer_ = nullptr;
 };

@@ -351,6 +351,32 @@ def test_krylov_expm_vs_eigh(dt, z):
     assert st["matvecs"] >= 1 and st["substeps"] >= 1
 
 
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+@pytest.mark.parametrize("reorth", [0, 1, 2, 3])
+def test_krylov_reorthogonalisation_modes_vs_eigh(dt, reorth):
+    """Every reorthogonalisation mode (none, local, full CGS2, partial after Simon) on a
+    long Lanczos run (N = 20: 512-dimensional blocks, m = 128, |z| far beyond one short
+    sub-step) against the eigendecomposition; full mode reorthogonalises every step, partial
+    mode some but not all, the others none."""
+    N, k, seed = 20, 4, 8
+    subs, J, _ = ensemble.sample_terms(N, k, seed)
+    HD = dense.blocks(dense.hamiltonian(N, subs, J))[0]
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    v = inputs.complex_vector(HD.shape[0], 12)[0]
+    vd = dev(v, cdt(dt))
+    out = torch.empty_like(vd)
+    z = -120.0j
+    st = syk.krylov_expm(h, 0, z, vd, out, m=128, reorth=reorth)
+    ref = dense.Eig(HD).expm_apply(z, host(vd))
+    assert rel(host(out), ref) <= (1e-10 if dt == syk.C128 else 1e-5), st
+    if reorth == 2:
+        assert st["reorths"] == st["matvecs"]
+    elif reorth == 3:
+        assert 1 <= st["reorths"] < st["matvecs"], st
+    else:
+        assert st["reorths"] == 0
+
+
 def test_krylov_in_place_and_unitary():
     h = syk.create_hamiltonian(30, 4, 4, 3)
     n = 1 << 14
