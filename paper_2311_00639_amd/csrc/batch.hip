@@ -140,14 +140,19 @@ __device__ __forceinline__ void bsum2(double &a, double &b, LShared<NT> &sh, uin
 // ------------------------------------------------------------------ vector kernels
 // Thread tid owns amplitudes r * NT + tid, r < R = 2^L / NT.
 
+// One term on a thread's RC registers.  xr and zr are wave-uniform: the partner register
+// offset (r ^ xr) << LNT and the register sign are scalar values, so each register costs
+// one vector add for its LDS address and one vector XOR for its sign besides the FMAs.
 template <int NT, int RC, bool IM>
-__device__ __forceinline__ void term_regs(float2 (&acc)[RC], const lf2 *buf, float cl, uint32_t lane, uint32_t xr,
+__device__ __forceinline__ void term_regs(float2 (&acc)[RC], const lf2 *buf_lane, float cl, uint32_t xr,
                                           uint32_t zr) {
     constexpr int LNT = __builtin_ctz(NT);
 #pragma unroll
     for (int r = 0; r < RC; ++r) {
-        const float2 q = ld(buf + (((static_cast<uint32_t>(r) ^ xr) << LNT) | lane));
-        const float cr = fsign(cl, __popc(static_cast<uint32_t>(r) & zr) & 1u);
+        const float2 q = ld(buf_lane + ((static_cast<uint32_t>(r) ^ xr) << LNT));
+        uint32_t sg = (__popc(static_cast<uint32_t>(r) & zr) & 1u) << 31;
+        asm("" : "+s"(sg));              // keep the register sign a scalar operand
+        const float cr = r == 0 ? cl : __int_as_float(__float_as_int(cl) ^ static_cast<int>(sg));
         if (IM) {
             acc[r].x -= cr * q.y;
             acc[r].y += cr * q.x;
@@ -177,7 +182,7 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
     const int K = c.job.K;
     double dre = 0.0;
     // one term with wave-uniform fields (scalar registers)
-    auto term = [&](float2 (&acc)[RC], uint32_t tx, uint32_t tz, float tc, uint32_t timag, int o) __attribute__((always_inline)) {
+    auto term = [&](auto im, float2 (&acc)[RC], uint32_t tx, uint32_t tz, float tc, int o) __attribute__((always_inline)) {
         const uint32_t xl = tx & (CH - 1);
         const uint32_t lane = tid ^ (xl & (NT - 1));
         const uint32_t xr = xl >> LNT;
@@ -185,10 +190,21 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
         // sign of output m = (o RC + r) NT + tid: thread bits, chunk bits, register bits
         const uint32_t par = (__popc(tid & tz & (NT - 1)) + __popc((tz >> LCH) & static_cast<uint32_t>(o))) & 1u;
         const float cl = fsign(tc, par);
-        if (timag)
-            term_regs<NT, RC, true>(acc, c.buf, cl, lane, xr, zr);
+        term_regs<NT, RC, decltype(im)::value>(acc, c.buf + lane, cl, xr, zr);
+    };
+    // the terms of [lo, hi) with the given phase, from LDS or from memory; the two phases
+    // run as separate loops so that each loop body is one straight FMA sequence
+    const bool staged = __builtin_amdgcn_readfirstlane(lterms != nullptr ? 1 : 0) != 0;   // uniform
+    auto phase = [&](auto im, float2 (&acc)[RC], int lo, int hi, int o) __attribute__((always_inline)) {
+        auto one = [&](const BatchTerm &tm) __attribute__((always_inline)) {
+            if ((__builtin_amdgcn_readfirstlane(tm.imag) != 0) != decltype(im)::value) return;
+            term(im, acc, __builtin_amdgcn_readfirstlane(tm.x), __builtin_amdgcn_readfirstlane(tm.z),
+                 __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tm.c))), o);
+        };
+        if (staged)
+            for (int t = lo; t < hi; ++t) one(ld(lterms + t));
         else
-            term_regs<NT, RC, false>(acc, c.buf, cl, lane, xr, zr);
+            for (int t = lo; t < hi; ++t) one(ld(terms + t));
     };
     for (int o = 0; o < NCH; ++o) {
         float2 acc[RC];
@@ -207,19 +223,8 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
                 lo = c.job.gstart[blk][want << SH];
                 hi = c.job.gstart[blk][(want + 1) << SH];
             }
-            if (lterms) {
-                for (int t = lo; t < hi; ++t) {
-                    const BatchTerm tm = ld(lterms + t);
-                    term(acc, __builtin_amdgcn_readfirstlane(tm.x), __builtin_amdgcn_readfirstlane(tm.z),
-                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(tm.c))),
-                         __builtin_amdgcn_readfirstlane(tm.imag), o);
-                }
-            } else {
-                for (int t = lo; t < hi; ++t) {
-                    const BatchTerm tm = ld(terms + t);
-                    term(acc, tm.x, tm.z, tm.c, tm.imag, o);
-                }
-            }
+            phase(std::false_type{}, acc, lo, hi, o);
+            phase(std::true_type{}, acc, lo, hi, o);
         }
 #pragma unroll
         for (int r = 0; r < RC; ++r) {
