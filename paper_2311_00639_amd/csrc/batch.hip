@@ -537,7 +537,7 @@ __device__ void prop(Ctx<NT, CHB> &c, int blk, double zr, double zi, gf2 *v) {
             ++c.matvecs;
             k = j + 1;
             if (k < next && k < m) continue;
-            next = k + (k / 4 > 2 ? k / 4 : 2);
+            next = k + 1;
             if (c.tid < 64) decide<NT>(c.sh, k, m, remaining, zr, zi, c.p.tol, c.tid);
             __syncthreads();
             done = c.sh.ctl_i[0];
