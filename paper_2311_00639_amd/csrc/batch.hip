@@ -89,6 +89,7 @@ struct Shared {
     double red[4][NT / 64];
     double al[kMaxKrylov + 2];
     double bt[kMaxKrylov + 2];
+    float sc[kMaxKrylov + 2];          // basis vector i is stored as beta_{i-1} v_i: v_i = sc[i] * stored
     double cre[kMaxKrylov + 2], cim[kMaxKrylov + 2];
     double fre[kCheb], fim[kCheb];
     double cosb[4 * kCheb];            // cos(pi j / (2 kCheb)), j < 4 kCheb
@@ -168,7 +169,7 @@ __device__ __forceinline__ void term_regs(float2 (&acc)[RC], const lf2 *buf_lane
 // registers (RC per thread) while every chunk ch of v is staged in LDS in turn, and the
 // terms whose partner offset x >> log2(CH) equals o ^ ch are applied from it.
 template <int NT, int CHB, int L>
-__device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
+__device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y, float vs) {
     constexpr int n = 1 << L;
     constexpr int LCH = L < CHB ? L : CHB;
     constexpr int CH = 1 << LCH;
@@ -213,7 +214,10 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
         for (int ch = 0; ch < NCH; ++ch) {
             __syncthreads();                              // earlier readers of buf are done
 #pragma unroll
-            for (int r = 0; r < RC; ++r) st(c.buf + (r * NT + tid), ld(v + (ch * CH + r * NT + tid)));
+            for (int r = 0; r < RC; ++r) {
+                const float2 q = ld(v + (ch * CH + r * NT + tid));
+                st(c.buf + (r * NT + tid), float2{vs * q.x, vs * q.y});
+            }
             __syncthreads();
             // the terms with partner chunk offset x >> LCH == o ^ ch (terms sorted by x)
             const uint32_t want = static_cast<uint32_t>(o ^ ch);
@@ -230,7 +234,7 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y) {
         for (int r = 0; r < RC; ++r) {
             const int i = o * CH + r * NT + static_cast<int>(tid);
             const float2 q = ld(v + i);
-            dre += static_cast<double>(q.x) * acc[r].x + static_cast<double>(q.y) * acc[r].y;
+            dre += static_cast<double>(vs * q.x) * acc[r].x + static_cast<double>(vs * q.y) * acc[r].y;
             st(y + i, acc[r]);
         }
     }
@@ -339,11 +343,15 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
     const gf2 *vj = c.basis + static_cast<size_t>(j) * c.p.vec_stride;
     const gf2 *vp = j > 0 ? c.basis + static_cast<size_t>(j - 1) * c.p.vec_stride : nullptr;
     gf2 *vn = c.basis + static_cast<size_t>(j + 1) * c.p.vec_stride;
-    double a = apply_h<NT, CHB, L>(c, blk, vj, vn), dummy = 0.0;
+    // basis slots hold v_i / sc[i]; the next slot is left unnormalised (its scale 1/beta_j
+    // enters wherever it is read), which saves a normalising pass per step
+    const float sj = c.sh.sc[j];
+    const float sp = j > 0 ? c.sh.sc[j - 1] : 0.0f;
+    double a = apply_h<NT, CHB, L>(c, blk, vj, vn, sj), dummy = 0.0;
     bsum2<NT>(a, dummy, c.sh, c.tid);
     const double alpha = a;
     const double bprev = c.sh.bt[j];
-    const float fa = static_cast<float>(alpha), fb = static_cast<float>(bprev);
+    const float fa = static_cast<float>(alpha) * sj, fb = static_cast<float>(bprev) * sp;
     double w2 = 0.0;
     dummy = 0.0;
 #pragma unroll 4
@@ -363,16 +371,10 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
     }
     bsum2<NT>(w2, dummy, c.sh, c.tid);
     const double beta = sqrt(w2);
-    const float inv = beta > 0.0 ? static_cast<float>(1.0 / beta) : 0.0f;
-#pragma unroll 4
-    for (int r = 0; r < R; ++r) {
-        const int i = r * NT + static_cast<int>(c.tid);
-        const float2 w = ld(vn + i);
-        st(vn + i, float2{w.x * inv, w.y * inv});
-    }
     if (c.tid == 0) {
         c.sh.al[j] = alpha;
         c.sh.bt[j + 1] = beta;
+        c.sh.sc[j + 1] = beta > 0.0 ? static_cast<float>(1.0 / beta) : 0.0f;
     }
     __syncthreads();
 }
@@ -528,7 +530,10 @@ __device__ void prop(Ctx<NT, CHB> &c, int blk, double zr, double zi, gf2 *v) {
             return;
         }
         scale_copy<NT, CHB, L>(c, v, c.basis, 1.0 / nrm);
-        if (c.tid == 0) c.sh.bt[0] = 0.0;
+        if (c.tid == 0) {
+            c.sh.bt[0] = 0.0;
+            c.sh.sc[0] = 1.0f;
+        }
         __syncthreads();
         int k = 0, next = 4, done = 0;
         double tau = 0.0;
@@ -560,7 +565,7 @@ __device__ void prop(Ctx<NT, CHB> &c, int blk, double zr, double zi, gf2 *v) {
             double sr = 0.0, si = 0.0;
             for (int i = 0; i < k; ++i) {
                 const float2 q = ld(c.basis + (static_cast<size_t>(i) * c.p.vec_stride + r * NT + c.tid));
-                const double cr = c.sh.cre[i], ci = c.sh.cim[i];
+                const double cr = c.sh.cre[i] * c.sh.sc[i], ci = c.sh.cim[i] * c.sh.sc[i];
                 sr += cr * q.x - ci * q.y;
                 si += cr * q.y + ci * q.x;
             }
