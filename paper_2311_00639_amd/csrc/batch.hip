@@ -138,6 +138,19 @@ __device__ __forceinline__ void bsum2(double &a, double &b, LShared<NT> &sh, uin
     __syncthreads();
 }
 
+// sum of one double over the workgroup, same value and order in every thread
+template <int NT>
+__device__ __forceinline__ double bsum1(double a, LShared<NT> &sh, uint32_t tid) {
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    if ((tid & 63) == 0) sh.red[0][tid >> 6] = a;
+    __syncthreads();
+    a = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) a += sh.red[0][w];
+    __syncthreads();
+    return a;
+}
+
 // ------------------------------------------------------------------ vector kernels
 // Thread tid owns amplitudes r * NT + tid, r < R = 2^L / NT.
 
@@ -244,14 +257,13 @@ __device__ double apply_h(Ctx<NT, CHB> &c, int blk, const gf2 *v, gf2 *y, float 
 template <int NT, int CHB, int L>
 __device__ double norm2(Ctx<NT, CHB> &c, const gf2 *v) {
     constexpr int R = (1 << L) / NT;
-    double a = 0.0, b = 0.0;
+    double a = 0.0;
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
         const float2 q = ld(v + (r * NT + c.tid));
         a += static_cast<double>(q.x) * q.x + static_cast<double>(q.y) * q.y;
     }
-    bsum2<NT>(a, b, c.sh, c.tid);
-    return a;
+    return bsum1<NT>(a, c.sh, c.tid);
 }
 
 // <u, v> = sum conj(u) v
@@ -314,7 +326,7 @@ template <int NT, int CHB, int L>
 __device__ void haar(Ctx<NT, CHB> &c, int A, gf2 *dst) {
     constexpr int R = (1 << L) / NT;
     const uint64_t h = 1ULL << L;
-    double a = 0.0, b = 0.0;
+    double a = 0.0;
 #pragma unroll 2
     for (int r = 0; r < R; ++r) {
         const uint64_t m = static_cast<uint64_t>(r * NT + c.tid);
@@ -324,7 +336,7 @@ __device__ void haar(Ctx<NT, CHB> &c, int A, gf2 *dst) {
         const double2 s = A == 0 ? u : d;
         st(dst + m, float2{static_cast<float>(s.x), static_cast<float>(s.y)});
     }
-    bsum2<NT>(a, b, c.sh, c.tid);
+    a = bsum1<NT>(a, c.sh, c.tid);
     const double inv = 1.0 / sqrt(a);
 #pragma unroll 2
     for (int r = 0; r < R; ++r) {
@@ -347,13 +359,10 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
     // enters wherever it is read), which saves a normalising pass per step
     const float sj = c.sh.sc[j];
     const float sp = j > 0 ? c.sh.sc[j - 1] : 0.0f;
-    double a = apply_h<NT, CHB, L>(c, blk, vj, vn, sj), dummy = 0.0;
-    bsum2<NT>(a, dummy, c.sh, c.tid);
-    const double alpha = a;
+    const double alpha = bsum1<NT>(apply_h<NT, CHB, L>(c, blk, vj, vn, sj), c.sh, c.tid);
     const double bprev = c.sh.bt[j];
     const float fa = static_cast<float>(alpha) * sj, fb = static_cast<float>(bprev) * sp;
     double w2 = 0.0;
-    dummy = 0.0;
 #pragma unroll 4
     for (int r = 0; r < R; ++r) {
         const int i = r * NT + static_cast<int>(c.tid);
@@ -369,8 +378,7 @@ __device__ void lanczos_step(Ctx<NT, CHB> &c, int blk, int j) {
         st(vn + i, w);
         w2 += static_cast<double>(w.x) * w.x + static_cast<double>(w.y) * w.y;
     }
-    bsum2<NT>(w2, dummy, c.sh, c.tid);
-    const double beta = sqrt(w2);
+    const double beta = sqrt(bsum1<NT>(w2, c.sh, c.tid));
     if (c.tid == 0) {
         c.sh.al[j] = alpha;
         c.sh.bt[j + 1] = beta;
