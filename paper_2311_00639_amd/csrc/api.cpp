@@ -702,7 +702,10 @@ syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int 
         *out = syk_plan_desc{};
         const bool c64 = dt == SYK_C64;
         out->tiled = c64 ? syk::use_tiled<float>(H.L) : syk::use_tiled<double>(H.L);
-        if (!out->tiled) return;
+        if (!out->tiled) {
+            out->n_groups = syk::gather_groups(H.block_terms[blk]);
+            return;
+        }
         const int var = c64 ? H.variant<float>() : H.variant<double>();
         const syk::TiledVariant tv = c64 ? syk::tiled_variants<float>()[var] : syk::tiled_variants<double>()[var];
         const int bt = tv.bt, rb = tv.rb;

@@ -42,12 +42,18 @@ struct DeviceTables {            // per device, per block: real terms first, the
     double *c64 = nullptr;
     int n_real = 0;
     int K = 0;
+    // grouped by x mask for the gather kernel, when that saves at least half of its
+    // gathers (G > 0): group g has mask gx[g], real-phase terms [gs[g], gm[g]) and i-phase
+    // terms [gm[g], gs[g + 1]) of gz / gc32 / gc64
+    uint32_t *gx = nullptr, *gs = nullptr, *gm = nullptr, *gz = nullptr;
+    float *gc32 = nullptr;
+    double *gc64 = nullptr;
+    int G = 0;
 };
 
-// Compiled variants of the tiled apply_H kernel: 2^bt amplitudes per output tile,
-// 2^rb register-held outputs per thread (2^(bt-rb) threads per workgroup), nbuf LDS
-// buffers of one partner tile each (at most 128 KiB of the 160 KiB per CU), pf = nbuf - 1
-// partner tiles in flight.  The autotuner times them on the actual Hamiltonian.
+// distinct x masks of a block's terms if the gather kernel groups them (K >= 2 G), else 0
+int gather_groups(const std::vector<BlockTerm> &terms);
+
 // Compiled variant of the tiled apply_H kernel: tiles of 2^bt amplitudes, 2^rb per
 // thread, nbuf LDS partner buffers (nbuf - 1 copies in flight; 1 = copy, then compute),
 // pf extra partner entries at the end of the group list, occ workgroups resident per CU

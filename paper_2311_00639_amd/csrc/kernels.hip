@@ -84,16 +84,53 @@ __global__ void __launch_bounds__(kBlock) apply_h_gather(const uint32_t *__restr
     }
 }
 
+// Terms grouped by x mask (dense and near-dense Hamiltonians, many terms per mask): per
+// output amplitude and group, the diagonal D_x(m) = sum_t c_t (-1)^popc(m & z_t) is summed
+// over the group's real-phase terms (Re) and i-phase terms (Im), then multiplied once by
+// the gathered partner x[m ^ x].  One gather per group instead of one per term.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) apply_h_grouped(const uint32_t *__restrict__ gx,
+                                                          const uint32_t *__restrict__ gs,
+                                                          const uint32_t *__restrict__ gm,
+                                                          const uint32_t *__restrict__ gz,
+                                                          const T *__restrict__ gc, int G,
+                                                          const V2<T> *__restrict__ x, V2<T> *__restrict__ y,
+                                                          uint32_t n_amps, uint64_t ld) {
+    const uint64_t vo = static_cast<uint64_t>(blockIdx.y) * ld;
+    x += vo;
+    y += vo;
+    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < n_amps; m += gridDim.x * kBlock) {
+        T ar = 0, ai = 0;
+        for (int g = 0; g < G; ++g) {
+            const V2<T> v = x[m ^ gx[g]];
+            const uint32_t t0 = gs[g], t1 = gm[g], t2 = gs[g + 1];
+            T dre = 0, dim = 0;
+            for (uint32_t t = t0; t < t1; ++t) dre += (__popc(m & gz[t]) & 1) ? -gc[t] : gc[t];
+            for (uint32_t t = t1; t < t2; ++t) dim += (__popc(m & gz[t]) & 1) ? -gc[t] : gc[t];
+            ar += dre * v.x - dim * v.y;
+            ai += dre * v.y + dim * v.x;
+        }
+        y[m] = V2<T>{ar, ai};
+    }
+}
+
 template <typename T> static const T *coef_ptr(const DeviceTables &tb);
 template <> const float *coef_ptr<float>(const DeviceTables &tb) { return tb.c32; }
 template <> const double *coef_ptr<double>(const DeviceTables &tb) { return tb.c64; }
+template <typename T> static const T *gcoef_ptr(const DeviceTables &tb);
+template <> const float *gcoef_ptr<float>(const DeviceTables &tb) { return tb.gc32; }
+template <> const double *gcoef_ptr<double>(const DeviceTables &tb) { return tb.gc64; }
 
 template <typename T>
 void launch_apply_h(const DeviceTables &tb, const T *x, T *y, uint32_t n_amps, int nvec, uint64_t ld,
                     hipStream_t s) {
     dim3 grid(grid_for(n_amps), nvec);
-    hipLaunchKernelGGL(apply_h_gather<T>, grid, dim3(kBlock), 0, s, tb.x, tb.z, coef_ptr<T>(tb), tb.n_real, tb.K,
-                       reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
+    if (tb.G > 0)
+        hipLaunchKernelGGL(apply_h_grouped<T>, grid, dim3(kBlock), 0, s, tb.gx, tb.gs, tb.gm, tb.gz, gcoef_ptr<T>(tb),
+                           tb.G, reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
+    else
+        hipLaunchKernelGGL(apply_h_gather<T>, grid, dim3(kBlock), 0, s, tb.x, tb.z, coef_ptr<T>(tb), tb.n_real, tb.K,
+                           reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
     SYK_HIP(hipGetLastError());
 }
 

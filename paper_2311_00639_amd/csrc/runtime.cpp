@@ -1,4 +1,5 @@
 // Host runtime of libsyk: error reporting, device term tables, device workspaces.
+#include <algorithm>
 #include <cstring>
 #include <map>
 #include <thread>
@@ -22,7 +23,28 @@ static void free_tables(DeviceTables &t) {
     hipFree(t.z);
     hipFree(t.c32);
     hipFree(t.c64);
+    hipFree(t.gx);
+    hipFree(t.gs);
+    hipFree(t.gm);
+    hipFree(t.gz);
+    hipFree(t.gc32);
+    hipFree(t.gc64);
     t = DeviceTables{};
+}
+
+int gather_groups(const std::vector<BlockTerm> &terms) {
+    std::vector<uint32_t> xs;
+    xs.reserve(terms.size());
+    for (const BlockTerm &t : terms) xs.push_back(t.x);
+    std::sort(xs.begin(), xs.end());
+    const int G = static_cast<int>(std::unique(xs.begin(), xs.end()) - xs.begin());
+    return static_cast<int>(terms.size()) >= 2 * G ? G : 0;
+}
+
+template <typename U>
+static void upload_vec(U *&d, const std::vector<U> &h) {
+    SYK_HIP(hipMalloc(reinterpret_cast<void **>(&d), std::max<size_t>(h.size(), 1) * sizeof(U)));
+    if (!h.empty()) SYK_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice));
 }
 
 const DeviceTables &Hamiltonian::tables(int blk) {
@@ -59,6 +81,43 @@ const DeviceTables &Hamiltonian::tables(int blk) {
     }
     nt.n_real = n_real[blk];
     nt.K = K;
+    if (gather_groups(bt) > 0) {
+        // terms ordered by (x, phase): one gather per x group, the group's real- and
+        // i-phase coefficients summed per amplitude before the multiply
+        std::vector<int> order(K);
+        for (int a = 0; a < K; ++a) order[a] = a;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return bt[a].x != bt[b].x ? bt[a].x < bt[b].x : (!bt[a].imag && bt[b].imag);
+        });
+        std::vector<uint32_t> gx, gs, gm, gz(K);
+        std::vector<float> gc32(K);
+        std::vector<double> gc64(K);
+        for (int i = 0; i < K; ++i) {
+            const BlockTerm &t = bt[order[i]];
+            if (i == 0 || t.x != bt[order[i - 1]].x) {
+                gx.push_back(t.x);
+                gs.push_back(static_cast<uint32_t>(i));
+                gm.push_back(static_cast<uint32_t>(i));
+            }
+            if (!t.imag) gm.back() = static_cast<uint32_t>(i + 1);
+            gz[i] = t.z;
+            gc64[i] = t.c;
+            gc32[i] = static_cast<float>(t.c);
+        }
+        gs.push_back(static_cast<uint32_t>(K));
+        try {
+            upload_vec(nt.gx, gx);
+            upload_vec(nt.gs, gs);
+            upload_vec(nt.gm, gm);
+            upload_vec(nt.gz, gz);
+            upload_vec(nt.gc32, gc32);
+            upload_vec(nt.gc64, gc64);
+        } catch (...) {
+            free_tables(nt);
+            throw;
+        }
+        nt.G = static_cast<int>(gx.size());
+    }
     t = nt;
     return t;
 }

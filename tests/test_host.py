@@ -361,3 +361,22 @@ def test_bench_refuses_more_than_one_gpu():
                        timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_gather_kernel_groups_terms_by_x_mask_when_it_pays():
+    """Blocks below the tiled size: the gather kernel groups terms by x mask (one gather
+    per distinct mask) when there are at least twice as many terms as masks, e.g. dense SYK;
+    sparse Hamiltonians keep one gather per term.  The group count equals the number of
+    distinct x masks of the block's terms."""
+    for N, k, ens, grouped in [(16, math.comb(16, 4) / 16, syk.BERNOULLI, True), (30, math.comb(30, 4) / 30,
+                                                                              syk.BERNOULLI, True),
+                               (16, 4, syk.EXACT_K, False), (30, 40, syk.EXACT_K, False)]:
+        h = syk.create_hamiltonian(N, 4, k, 3, ens)
+        for blk in (0, 1):
+            d = syk.plan_describe(h, blk, syk.C64, -1)
+            assert d["tiled"] == 0
+            masks = len(set(int(v) for v in h.terms()["xmask"]))
+            if grouped:
+                assert d["n_groups"] == masks and h.info()["K"] >= 2 * masks
+            else:
+                assert d["n_groups"] == 0
