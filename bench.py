@@ -228,7 +228,8 @@ def next_rows_leg(syk, h, stream):
     * green: the Green function G_R(t) of chi_55 on the benchmark realisation (N = 56,
       k = 4, beta = 10, t = 0:0.25:5, complex64, Krylov dim 60, tol 3e-6);
     * dense: one apply_H of dense SYK (p = 1, K = C(38,4) = 73815) at N = 38, best
-      autotuned variant, with its VALU-floor fraction;
+      autotuned variant, with its VALU-floor fraction; dense_gather: the same at N = 30
+      (K = 27405), below the tiled size, where the gather kernel groups terms by x mask;
     * spin_operator: a transverse-field Ising chain on 27 qubits (sum Z_q Z_{q+1} + 0.7 sum X_q)
       through syk_op_to_hamiltonian: one apply_H (best variant) and one e^{-iH} propagation."""
     import math
@@ -254,6 +255,25 @@ def next_rows_leg(syk, h, stream):
     out["dense"] = {"N": nd, "K": info["K"], "variant": variant, "ms": best, "term_amps_per_s": ta / (best * 1e-3),
                     "valu_floor_frac": ta / 3.93e13 / (best * 1e-3), "variant_ms": ms}
     hd.close()
+    # below the tiled size: the gather kernel with terms grouped by x mask
+    ng = 30
+    hg = syk.create_hamiltonian(ng, 4, math.comb(ng, 4) / ng, 2, syk.BERNOULLI)
+    info = hg.info()
+    x = torch.randn(info["block_dim"], dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    syk.apply_H(hg, 0, x, y, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(20):
+        syk.apply_H(hg, 0, x, y, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1) / 20
+    ta = info["K"] * info["block_dim"]
+    out["dense_gather"] = {"N": ng, "K": info["K"], "x_mask_groups": syk.plan_describe(hg, 0, syk.C64, -1)["n_groups"],
+                           "ms": gms, "term_amps_per_s": ta / (gms * 1e-3)}
+    del x, y
+    hg.close()
 
     L, g = 27, 0.7
     xs, zs, cs = [], [], []

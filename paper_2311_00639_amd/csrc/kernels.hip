@@ -87,8 +87,12 @@ __global__ void __launch_bounds__(kBlock) apply_h_gather(const uint32_t *__restr
 // Terms grouped by x mask (dense and near-dense Hamiltonians, many terms per mask): per
 // output amplitude and group, the diagonal D_x(m) = sum_t c_t (-1)^popc(m & z_t) is summed
 // over the group's real-phase terms (Re) and i-phase terms (Im), then multiplied once by
-// the gathered partner x[m ^ x].  One gather per group instead of one per term.
-template <typename T>
+// the gathered partner x[m ^ x].  One gather per group instead of one per term.  Small
+// blocks have too few amplitudes to fill the GPU, so a workgroup of kBlock threads holds
+// A = kBlock / S amplitudes and S slices of the group list (slice s takes groups s, s + S,
+// ...); the slices' sums are added in slice order in LDS, so the result does not depend on
+// scheduling.
+template <typename T, int S>
 __global__ void __launch_bounds__(kBlock) apply_h_grouped(const uint32_t *__restrict__ gx,
                                                           const uint32_t *__restrict__ gs,
                                                           const uint32_t *__restrict__ gm,
@@ -96,21 +100,42 @@ __global__ void __launch_bounds__(kBlock) apply_h_grouped(const uint32_t *__rest
                                                           const T *__restrict__ gc, int G,
                                                           const V2<T> *__restrict__ x, V2<T> *__restrict__ y,
                                                           uint32_t n_amps, uint64_t ld) {
+    constexpr int A = kBlock / S;
+    __shared__ V2<T> part[S > 1 ? S : 1][A];
     const uint64_t vo = static_cast<uint64_t>(blockIdx.y) * ld;
     x += vo;
     y += vo;
-    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < n_amps; m += gridDim.x * kBlock) {
+    const int slice = static_cast<int>(threadIdx.x) / A, a = static_cast<int>(threadIdx.x) % A;
+    for (uint32_t base = blockIdx.x * A; base < n_amps; base += gridDim.x * A) {
+        const uint32_t m = base + a;
         T ar = 0, ai = 0;
-        for (int g = 0; g < G; ++g) {
-            const V2<T> v = x[m ^ gx[g]];
-            const uint32_t t0 = gs[g], t1 = gm[g], t2 = gs[g + 1];
-            T dre = 0, dim = 0;
-            for (uint32_t t = t0; t < t1; ++t) dre += (__popc(m & gz[t]) & 1) ? -gc[t] : gc[t];
-            for (uint32_t t = t1; t < t2; ++t) dim += (__popc(m & gz[t]) & 1) ? -gc[t] : gc[t];
-            ar += dre * v.x - dim * v.y;
-            ai += dre * v.y + dim * v.x;
+        if (m < n_amps) {
+            for (int g = slice; g < G; g += S) {
+                const V2<T> v = x[m ^ gx[g]];
+                const uint32_t t0 = gs[g], t1 = gm[g], t2 = gs[g + 1];
+                T dre = 0, dim = 0;
+                for (uint32_t t = t0; t < t1; ++t) dre += (__popc(m & gz[t]) & 1) ? -gc[t] : gc[t];
+                for (uint32_t t = t1; t < t2; ++t) dim += (__popc(m & gz[t]) & 1) ? -gc[t] : gc[t];
+                ar += dre * v.x - dim * v.y;
+                ai += dre * v.y + dim * v.x;
+            }
         }
-        y[m] = V2<T>{ar, ai};
+        if constexpr (S == 1) {
+            if (m < n_amps) y[m] = V2<T>{ar, ai};
+        } else {
+            part[slice][a] = V2<T>{ar, ai};
+            __syncthreads();
+            if (slice == 0 && m < n_amps) {
+                V2<T> acc = part[0][a];
+#pragma unroll
+                for (int k = 1; k < S; ++k) {
+                    acc.x += part[k][a].x;
+                    acc.y += part[k][a].y;
+                }
+                y[m] = acc;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -125,10 +150,25 @@ template <typename T>
 void launch_apply_h(const DeviceTables &tb, const T *x, T *y, uint32_t n_amps, int nvec, uint64_t ld,
                     hipStream_t s) {
     dim3 grid(grid_for(n_amps), nvec);
-    if (tb.G > 0)
-        hipLaunchKernelGGL(apply_h_grouped<T>, grid, dim3(kBlock), 0, s, tb.gx, tb.gs, tb.gm, tb.gz, gcoef_ptr<T>(tb),
-                           tb.G, reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
-    else
+    if (tb.G > 0) {
+        // slices of the group list per amplitude: enough workgroups (about 1024) for small blocks
+        int S = 1;
+        while (S < 16 && static_cast<uint64_t>(n_amps) * S < 1024ull * kBlock) S *= 2;
+        const dim3 gg(static_cast<unsigned>((n_amps + kBlock / S - 1) / (kBlock / S)), nvec);
+        auto go = [&](auto sc) {
+            constexpr int SS = decltype(sc)::value;
+            hipLaunchKernelGGL((apply_h_grouped<T, SS>), gg, dim3(kBlock), 0, s, tb.gx, tb.gs, tb.gm, tb.gz,
+                               gcoef_ptr<T>(tb), tb.G, reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y),
+                               n_amps, ld);
+        };
+        switch (S) {
+            case 1: go(std::integral_constant<int, 1>{}); break;
+            case 2: go(std::integral_constant<int, 2>{}); break;
+            case 4: go(std::integral_constant<int, 4>{}); break;
+            case 8: go(std::integral_constant<int, 8>{}); break;
+            default: go(std::integral_constant<int, 16>{}); break;
+        }
+    } else
         hipLaunchKernelGGL(apply_h_gather<T>, grid, dim3(kBlock), 0, s, tb.x, tb.z, coef_ptr<T>(tb), tb.n_real, tb.K,
                            reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
     SYK_HIP(hipGetLastError());
