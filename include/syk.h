@@ -499,10 +499,9 @@ syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, doub
  * for the planner's choice (the layout syk_otoc uses by default), layout >= 0 for that
  * rotation. */
 typedef struct {
-    int tiled;             /* 0: the block is served by the per-amplitude gather kernel; then
-                              n_groups is the number of x-mask groups it gathers once each
-                              (terms grouped when K >= 2 n_groups, e.g. dense SYK), or 0 when
-                              it gathers once per term */
+    int tiled;             /* 0: the block is served by the gather kernel; then n_groups is the
+                              number of distinct x masks, each gathered once per amplitude
+                              (about K / 19 for dense SYK, about K for sparse) */
     int variant;           /* compiled kernel variant in use (default or tuned) */
     int tile_bits, rot, n_groups, classes_xcd, classes_gpu, res_bits;
     int tiles_per_wg;      /* output tiles a workgroup keeps in registers */

@@ -35,23 +35,18 @@ struct BlockTerm {
     bool imag;
 };
 
-struct DeviceTables {            // per device, per block: real terms first, then imaginary
-    uint32_t *x = nullptr;       // K entries
-    uint32_t *z = nullptr;
-    float *c32 = nullptr;
-    double *c64 = nullptr;
-    int n_real = 0;
+struct DeviceTables {            // per device, per block: the gather kernel's term tables
+    int n_real = 0;              // real-phase terms of the block
     int K = 0;
-    // grouped by x mask for the gather kernel, when that saves at least half of its
-    // gathers (G > 0): group g has mask gx[g], real-phase terms [gs[g], gm[g]) and i-phase
-    // terms [gm[g], gs[g + 1]) of gz / gc32 / gc64
+    // terms grouped by x mask: group g has mask gx[g], real-phase terms [gs[g], gm[g]) and
+    // i-phase terms [gm[g], gs[g + 1]) of gz / gc32 / gc64
     uint32_t *gx = nullptr, *gs = nullptr, *gm = nullptr, *gz = nullptr;
     float *gc32 = nullptr;
     double *gc64 = nullptr;
     int G = 0;
 };
 
-// distinct x masks of a block's terms if the gather kernel groups them (K >= 2 G), else 0
+// distinct x masks of a block's terms: the groups the gather kernel loads once each
 int gather_groups(const std::vector<BlockTerm> &terms);
 
 // Compiled variant of the tiled apply_H kernel: tiles of 2^bt amplitudes, 2^rb per

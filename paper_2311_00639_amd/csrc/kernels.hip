@@ -54,40 +54,11 @@ __device__ inline void block_sum(double (&v)[W], double *out) {
 }
 
 // ------------------------------------------------------------------ apply_H
-// One output amplitude per thread and loop over all terms: the partner x[m ^ x_a] is
-// gathered straight from global memory, the sign is the parity of m & z_a (the parity of
-// x_a & z_a is folded into c_a), real-phase terms first, then i-phase terms.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) apply_h_gather(const uint32_t *__restrict__ tx,
-                                                         const uint32_t *__restrict__ tz,
-                                                         const T *__restrict__ tc, int n_real, int K,
-                                                         const V2<T> *__restrict__ x, V2<T> *__restrict__ y,
-                                                         uint32_t n_amps, uint64_t ld) {
-    const uint64_t vo = static_cast<uint64_t>(blockIdx.y) * ld;
-    x += vo;
-    y += vo;
-    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < n_amps; m += gridDim.x * kBlock) {
-        T ar = 0, ai = 0;
-        for (int a = 0; a < n_real; ++a) {
-            const V2<T> v = x[m ^ tx[a]];
-            const T c = (__popc(m & tz[a]) & 1) ? -tc[a] : tc[a];
-            ar += c * v.x;
-            ai += c * v.y;
-        }
-        for (int a = n_real; a < K; ++a) {
-            const V2<T> v = x[m ^ tx[a]];
-            const T c = (__popc(m & tz[a]) & 1) ? -tc[a] : tc[a];
-            ar -= c * v.y;
-            ai += c * v.x;
-        }
-        y[m] = V2<T>{ar, ai};
-    }
-}
-
-// Terms grouped by x mask (dense and near-dense Hamiltonians, many terms per mask): per
-// output amplitude and group, the diagonal D_x(m) = sum_t c_t (-1)^popc(m & z_t) is summed
+// Blocks below the tiled size.  Terms are grouped by x mask (one term per mask for sparse
+// Hamiltonians, about 19 for dense SYK): per output amplitude and group, the diagonal
+// D_x(m) = sum_t c_t (-1)^popc(m & z_t) (the parity of x & z folded into c_t) is summed
 // over the group's real-phase terms (Re) and i-phase terms (Im), then multiplied once by
-// the gathered partner x[m ^ x].  One gather per group instead of one per term.  Small
+// the partner x[m ^ x] gathered straight from memory.  One gather per mask.  Small
 // blocks have too few amplitudes to fill the GPU, so a workgroup of kBlock threads holds
 // A = kBlock / S amplitudes and S slices of the group list (slice s takes groups s, s + S,
 // ...); the slices' sums are added in slice order in LDS, so the result does not depend on
@@ -139,9 +110,12 @@ __global__ void __launch_bounds__(kBlock) apply_h_grouped(const uint32_t *__rest
     }
 }
 
-template <typename T> static const T *coef_ptr(const DeviceTables &tb);
-template <> const float *coef_ptr<float>(const DeviceTables &tb) { return tb.c32; }
-template <> const double *coef_ptr<double>(const DeviceTables &tb) { return tb.c64; }
+template <typename T>
+__global__ void __launch_bounds__(kBlock) fill_zero(V2<T> *__restrict__ y, uint32_t n_amps, uint64_t ld) {
+    y += static_cast<uint64_t>(blockIdx.y) * ld;
+    for (uint32_t m = blockIdx.x * kBlock + threadIdx.x; m < n_amps; m += gridDim.x * kBlock) y[m] = V2<T>{T(0), T(0)};
+}
+
 template <typename T> static const T *gcoef_ptr(const DeviceTables &tb);
 template <> const float *gcoef_ptr<float>(const DeviceTables &tb) { return tb.gc32; }
 template <> const double *gcoef_ptr<double>(const DeviceTables &tb) { return tb.gc64; }
@@ -149,7 +123,6 @@ template <> const double *gcoef_ptr<double>(const DeviceTables &tb) { return tb.
 template <typename T>
 void launch_apply_h(const DeviceTables &tb, const T *x, T *y, uint32_t n_amps, int nvec, uint64_t ld,
                     hipStream_t s) {
-    dim3 grid(grid_for(n_amps), nvec);
     if (tb.G > 0) {
         // slices of the group list per amplitude: enough workgroups (about 1024) for small blocks
         int S = 1;
@@ -168,9 +141,10 @@ void launch_apply_h(const DeviceTables &tb, const T *x, T *y, uint32_t n_amps, i
             case 8: go(std::integral_constant<int, 8>{}); break;
             default: go(std::integral_constant<int, 16>{}); break;
         }
-    } else
-        hipLaunchKernelGGL(apply_h_gather<T>, grid, dim3(kBlock), 0, s, tb.x, tb.z, coef_ptr<T>(tb), tb.n_real, tb.K,
-                           reinterpret_cast<const V2<T> *>(x), reinterpret_cast<V2<T> *>(y), n_amps, ld);
+    } else {
+        hipLaunchKernelGGL(fill_zero<T>, dim3(grid_for(n_amps), nvec), dim3(kBlock), 0, s, reinterpret_cast<V2<T> *>(y),
+                           n_amps, ld);                        // no terms: H = 0
+    }
     SYK_HIP(hipGetLastError());
 }
 

@@ -19,10 +19,6 @@ void hip_check(hipError_t e, const char *what) {
 
 // ------------------------------------------------------------------ device tables
 static void free_tables(DeviceTables &t) {
-    hipFree(t.x);
-    hipFree(t.z);
-    hipFree(t.c32);
-    hipFree(t.c64);
     hipFree(t.gx);
     hipFree(t.gs);
     hipFree(t.gm);
@@ -37,8 +33,7 @@ int gather_groups(const std::vector<BlockTerm> &terms) {
     xs.reserve(terms.size());
     for (const BlockTerm &t : terms) xs.push_back(t.x);
     std::sort(xs.begin(), xs.end());
-    const int G = static_cast<int>(std::unique(xs.begin(), xs.end()) - xs.begin());
-    return static_cast<int>(terms.size()) >= 2 * G ? G : 0;
+    return static_cast<int>(std::unique(xs.begin(), xs.end()) - xs.begin());
 }
 
 template <typename U>
@@ -54,34 +49,12 @@ const DeviceTables &Hamiltonian::tables(int blk) {
     for (int b = 0; b < 2; ++b)
         if (static_cast<int>(this->dev[b].size()) <= dev) this->dev[b].resize(dev + 1);
     DeviceTables &t = this->dev[blk][dev];
-    if (t.x) return t;
+    if (t.gx) return t;
     const auto &bt = block_terms[blk];
-    std::vector<uint32_t> hx(K), hz(K);
-    std::vector<float> hc32(K);
-    std::vector<double> hc64(K);
-    for (int a = 0; a < K; ++a) {
-        hx[a] = bt[a].x;
-        hz[a] = bt[a].z;
-        hc64[a] = bt[a].c;
-        hc32[a] = static_cast<float>(bt[a].c);
-    }
     DeviceTables nt;
-    try {
-        SYK_HIP(hipMalloc(reinterpret_cast<void **>(&nt.x), K * sizeof(uint32_t)));
-        SYK_HIP(hipMalloc(reinterpret_cast<void **>(&nt.z), K * sizeof(uint32_t)));
-        SYK_HIP(hipMalloc(reinterpret_cast<void **>(&nt.c32), K * sizeof(float)));
-        SYK_HIP(hipMalloc(reinterpret_cast<void **>(&nt.c64), K * sizeof(double)));
-        SYK_HIP(hipMemcpy(nt.x, hx.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(nt.z, hz.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(nt.c32, hc32.data(), K * sizeof(float), hipMemcpyHostToDevice));
-        SYK_HIP(hipMemcpy(nt.c64, hc64.data(), K * sizeof(double), hipMemcpyHostToDevice));
-    } catch (...) {
-        free_tables(nt);
-        throw;
-    }
     nt.n_real = n_real[blk];
     nt.K = K;
-    if (gather_groups(bt) > 0) {
+    if (K > 0) {
         // terms ordered by (x, phase): one gather per x group, the group's real- and
         // i-phase coefficients summed per amplitude before the multiply
         std::vector<int> order(K);
@@ -292,7 +265,7 @@ Hamiltonian::~Hamiltonian() {
     bool have = hipGetDevice(&cur) == hipSuccess;
     for (int b = 0; b < 2; ++b) {
         for (size_t d = 0; d < dev[b].size(); ++d)
-            if (dev[b][d].x) {
+            if (dev[b][d].gx) {
                 if (have) hipSetDevice(static_cast<int>(d));
                 free_tables(dev[b][d]);
             }
