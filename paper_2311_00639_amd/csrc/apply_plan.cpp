@@ -413,12 +413,12 @@ static U *upload(const std::vector<U> &v) {
 }
 
 void free_plan(ApplyPlan &p) {
-    hipFree(p.pi);
-    hipFree(p.ranges);
-    hipFree(p.meta);
-    hipFree(p.tile_map);
-    hipFree(p.c32);
-    hipFree(p.c64);
+    ignore_status(hipFree(p.pi));
+    ignore_status(hipFree(p.ranges));
+    ignore_status(hipFree(p.meta));
+    ignore_status(hipFree(p.tile_map));
+    ignore_status(hipFree(p.c32));
+    ignore_status(hipFree(p.c64));
     p = ApplyPlan{};
 }
 

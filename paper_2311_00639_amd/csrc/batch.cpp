@@ -17,7 +17,7 @@ template <typename U>
 struct DevArray {
     U *p = nullptr;
     explicit DevArray(size_t n) { SYK_HIP(hipMalloc(reinterpret_cast<void **>(&p), std::max<size_t>(n, 1) * sizeof(U))); }
-    ~DevArray() { hipFree(p); }
+    ~DevArray() { ignore_status(hipFree(p)); }
     DevArray(const DevArray &) = delete;
     DevArray &operator=(const DevArray &) = delete;
 };
@@ -71,9 +71,10 @@ float run_once(const BatchVariant &v, BatchParams p, int n_jobs, int lmax, hipSt
     SYK_HIP(hipEventRecord(e1, s));
     SYK_HIP(hipEventSynchronize(e1));
     float ms = 0.0f;
-    hipEventElapsedTime(&ms, e0, e1);
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    const hipError_t te = hipEventElapsedTime(&ms, e0, e1);
+    ignore_status(hipEventDestroy(e0));
+    ignore_status(hipEventDestroy(e1));
+    SYK_HIP(te);
     (void)hold;
     return ms;
 }
@@ -182,7 +183,7 @@ void otoc_batch(const syk_batch_item *items, int n_items, const double *t, int n
         st.kernel_ms = run_once(vars[chosen], p, n_jobs, lmax, s, hold, ws, ws_cap, counter.p);
         st.slots = std::min(n_jobs, device_cus() * vars[chosen].occ);
     } catch (...) {
-        if (ws) hipFree(ws);
+        if (ws) ignore_status(hipFree(ws));
         throw;
     }
     SYK_HIP(hipFree(ws));

@@ -137,12 +137,12 @@ struct Engine::Impl {
             d.info.status = SYK_OK;
         } catch (const Error &e) {
             d.info.status = e.status;
-            hipStreamSynchronize(s);
+            ignore_status(hipStreamSynchronize(s));
         } catch (const std::bad_alloc &) {
             d.info.status = SYK_ENOMEM;
         } catch (...) {
             d.info.status = SYK_EDEVICE;
-            hipStreamSynchronize(s);
+            ignore_status(hipStreamSynchronize(s));
         }
         if (d.info.status != SYK_OK) {
             d.raw.assign(q.r.nt, 0.0);
@@ -190,7 +190,7 @@ struct Engine::Impl {
             cv_done.notify_all();
             cv_work.notify_all();                    // memory returned: others may fit now
         }
-        hipStreamDestroy(s);
+        ignore_status(hipStreamDestroy(s));
     }
 };
 

@@ -23,6 +23,9 @@ struct Error {
 [[noreturn]] void fail(syk_status s, const std::string &msg);
 void hip_check(hipError_t e, const char *what);
 #define SYK_HIP(call) ::syk::hip_check((call), #call)
+// Cleanup paths (destructors, unwinding after an error): a failure to release a resource
+// cannot be reported from there, so its status is dropped on purpose.
+inline void ignore_status(hipError_t) {}
 
 // ------------------------------------------------------------------ terms
 // One term of Eq. (1) on one parity block, reduced for the kernels:

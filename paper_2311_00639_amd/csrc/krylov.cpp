@@ -110,7 +110,7 @@ std::complex<double> TriExp::last(std::complex<double> z) const {
 
 // ------------------------------------------------------------------ apply_H timing
 ApplyTimer::~ApplyTimer() {
-    for (auto e : pool_) hipEventDestroy(e);
+    for (auto e : pool_) ignore_status(hipEventDestroy(e));
 }
 
 void ApplyTimer::begin(hipStream_t s) {

@@ -19,12 +19,12 @@ void hip_check(hipError_t e, const char *what) {
 
 // ------------------------------------------------------------------ device tables
 static void free_tables(DeviceTables &t) {
-    hipFree(t.gx);
-    hipFree(t.gs);
-    hipFree(t.gm);
-    hipFree(t.gz);
-    hipFree(t.gc32);
-    hipFree(t.gc64);
+    ignore_status(hipFree(t.gx));
+    ignore_status(hipFree(t.gs));
+    ignore_status(hipFree(t.gm));
+    ignore_status(hipFree(t.gz));
+    ignore_status(hipFree(t.gc32));
+    ignore_status(hipFree(t.gc64));
     t = DeviceTables{};
 }
 
@@ -245,14 +245,14 @@ int autotune(Hamiltonian &h, T *x, T *y, hipStream_t s, bool force, std::vector<
             }
         }
     } catch (...) {
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-        hipFree(part);
+        ignore_status(hipEventDestroy(e0));
+        ignore_status(hipEventDestroy(e1));
+        ignore_status(hipFree(part));
         throw;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipFree(part);
+    ignore_status(hipEventDestroy(e0));
+    ignore_status(hipEventDestroy(e1));
+    ignore_status(hipFree(part));
     std::lock_guard<std::mutex> g(h.dev_mu);
     h.tuned[{sizeof(T) == 8 ? 1 : 0, dev}] = best;
     return best;
@@ -266,16 +266,16 @@ Hamiltonian::~Hamiltonian() {
     for (int b = 0; b < 2; ++b) {
         for (size_t d = 0; d < dev[b].size(); ++d)
             if (dev[b][d].gx) {
-                if (have) hipSetDevice(static_cast<int>(d));
+                if (have) ignore_status(hipSetDevice(static_cast<int>(d)));
                 free_tables(dev[b][d]);
             }
     }
     for (auto &kv : plans)
         if (kv.second.pi) {
-            if (have) hipSetDevice(std::get<2>(kv.first));
+            if (have) ignore_status(hipSetDevice(std::get<2>(kv.first)));
             free_plan(kv.second);
         }
-    if (have) hipSetDevice(cur);
+    if (have) ignore_status(hipSetDevice(cur));
 }
 
 // ------------------------------------------------------------------ workspaces
@@ -291,7 +291,7 @@ void DeviceBuffer::ensure(size_t bytes) {
 }
 
 void DeviceBuffer::release() {
-    if (p_) hipFree(p_);
+    if (p_) ignore_status(hipFree(p_));
     p_ = nullptr;
     n_ = 0;
 }
