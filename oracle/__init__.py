@@ -20,6 +20,9 @@ dense      dense Majoranas, H, parity blocks, e^{zH} by eigh, the OTOC of Eq. (2
            function of the supplement.
 haar       counter-based Haar-random state over the full 2^(N/2) space.
 matfree    per-row matrix elements of H for sampled rows at any N (no dense matrix).
+commuting  closed forms for pairwise commuting terms: e^{zH} as a product of cosh/sinh
+           factors and the random-state OTOC of a lone Majorana pair, on the full vector
+           at any N it fits (Pauli strings applied one tensor axis at a time).
 
 Functions with no pin against the paper or mathematics are marked "parity unpinned"
 in their docstrings; at present there are none.

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import scipy.linalg
 
-from oracle import dense, ensemble, haar, lyapunov, matfree, pauli, splitmix
+from oracle import commuting, dense, ensemble, haar, lyapunov, matfree, pauli, splitmix
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -623,3 +623,90 @@ def test_ensemble_mean_and_standard_error():
     m, s = lyapunov.ensemble_mean(rows)
     assert np.allclose(m, rows.mean(axis=0)) and np.allclose(s, scipy.stats.sem(rows, axis=0), rtol=1e-13)
     assert np.all(lyapunov.ensemble_mean(rows[:1])[1] == 0.0)
+
+
+# --------------------------------------------------------------------------- commuting terms
+# Two sets of 4-subsets of range(12) whose gamma products commute pairwise (every pair shares
+# 0 or 2 indices), each with a term holding a pair (i, j) that no other term touches; the
+# second puts the pair on chi_{N-1}, chi_{N-2}.
+COMMUTING_N12 = [
+    ([(0, 1, 2, 3), (2, 3, 4, 5), (4, 5, 6, 7), (6, 7, 8, 9), (2, 3, 8, 9), (8, 9, 10, 11), (4, 5, 10, 11)], (0, 1)),
+    ([(0, 1, 2, 3), (0, 1, 8, 9), (2, 3, 4, 5), (4, 5, 6, 7), (6, 7, 8, 9), (8, 9, 10, 11)], (11, 10)),
+]
+
+
+def test_apply_string_matches_dense_kron():
+    """P v by one 2x2 contraction per tensor axis equals the dense Kronecker matrix times v."""
+    rng = np.random.default_rng(4)
+    n = 5
+    for _ in range(20):
+        s = (tuple(int(a) for a in rng.integers(0, 4, n)), int(rng.integers(0, 4)))
+        v = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+        assert np.abs(commuting.apply_string(s, v) - pauli.dense(s) @ v).max() < 1e-14
+
+
+def test_commutation_rule_matches_dense_products():
+    """gamma products of two 4-subsets commute iff the subsets share an even number of indices."""
+    N = 10
+    g = dense.gammas(N)
+    rng = np.random.default_rng(8)
+    seen = set()
+    for _ in range(60):
+        a, b = (tuple(sorted(rng.choice(N, 4, replace=False))) for _ in range(2))
+        Pa, Pb = g[a[0]] @ g[a[1]] @ g[a[2]] @ g[a[3]], g[b[0]] @ g[b[1]] @ g[b[2]] @ g[b[3]]
+        comm = np.abs(Pa @ Pb - Pb @ Pa).max() < 1e-12
+        assert comm == commuting.commute(a, b)
+        seen.add(comm)
+    assert seen == {True, False}
+
+
+@pytest.mark.parametrize("case", range(len(COMMUTING_N12)))
+def test_commuting_expm_matches_eigendecomposition(case):
+    """prod_b (cosh(z J_b/4) + sinh(z J_b/4) P_b) v equals e^{zH} v from the dense H by eigh."""
+    N = 12
+    subs, _ = COMMUTING_N12[case]
+    assert commuting.all_commute(subs)
+    J = np.random.default_rng(case).standard_normal(len(subs)) * 1.3
+    eg = dense.Eig(dense.hamiltonian(N, subs, J))
+    v = haar.haar_state(N, 31, case)
+    for z in (-2.5j, -1.7, 0.8 - 3.0j):
+        assert np.abs(commuting.expm_apply(N, subs, J, z, v) - eg.expm_apply(z, v)).max() < 1e-12
+
+
+@pytest.mark.parametrize("case", range(len(COMMUTING_N12)))
+@pytest.mark.parametrize("beta", [0.0, 3.0])
+def test_commuting_otoc_matches_dense_chain(case, beta):
+    """The closed form of the random-state OTOC equals the dense full-space chain of the
+    supplement's estimator (itself pinned above) for commuting terms and a lone pair."""
+    N = 12
+    subs, (i, j) = COMMUTING_N12[case]
+    J = np.random.default_rng(10 + case).standard_normal(len(subs)) * 1.3
+    H = dense.hamiltonian(N, subs, J)
+    ch = dense.chis(N)
+    psi = haar.haar_state(N, 7, case)
+    ts = [0.0, 0.3, 1.1, 2.6, 5.0]
+    ref = dense.otoc_state(H, ch[i], ch[j], beta, ts, psi)
+    got = commuting.otoc_state(N, subs, J, i, j, beta, ts, psi)
+    assert np.abs(got - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
+    if beta == 0.0:
+        assert abs(got[0] + 0.25) < 1e-13
+
+
+def test_commuting_closed_form_refuses_what_it_does_not_cover():
+    N = 12
+    subs, (i, j) = COMMUTING_N12[0]
+    J = np.ones(len(subs))
+    psi = haar.haar_state(N, 1, 0)
+    with pytest.raises(ValueError):
+        commuting.expm_apply(N, subs + [(0, 4, 6, 8)], list(J) + [1.0], -1.0, psi)   # shares 1 with (0,1,2,3)
+    with pytest.raises(ValueError):
+        commuting.otoc_state(N, subs, J, 2, 3, 0.0, [0.0], psi)                      # 2, 3 in several terms
+
+
+@pytest.mark.parametrize("N,K,seed,i,j", [(40, 6, 91, 39, 5), (40, 8, 188076, 39, 19)])
+def test_commuting_realisations_used_by_the_gpu_tests(N, K, seed, i, j):
+    """The seeds of the large-N commuting checks draw pairwise commuting terms with (i, j) a
+    lone pair, and at beta = 0, t = 0 the closed form is -1/4."""
+    subs, J, _ = ensemble.sample_terms(N, K / N, seed)
+    assert len(subs) == K and commuting.all_commute(subs)
+    assert commuting.lone_pair_term(subs, i, j) >= 0
