@@ -4,74 +4,88 @@ Workload (mixed precision at scale): N = 56 Majoranas (parity blocks of 2^27 amp
 q = 4, k = 4 (K = 224 terms), one disorder realisation (seed 56), complex64 state
 vectors with double Lanczos reductions and tridiagonal exponential, Krylov dimension 60,
 per-propagation tolerance 3e-6 (complex64 rounding, not the tolerance, sets the error of F;
-the mixed_precision leg reports it), one Haar state (state_seed 5600), W = chi_55, V = chi_54, beta in {5, 10, 20},
-t = 0, 0.25, ..., 20 (81 points).
+the mixed_precision leg reports it), one Haar state (state_seed 5600), W = chi_55,
+V = chi_54, t = 0, 0.25, ..., 20 (81 points); a realisation is the three curves at
+beta = 5, 10 and 20.
 
-A step is one complete OTOC curve (one beta, both parity-block chains, all 81 t points);
-steps cycle beta through 10, 5, 20, and a realisation is the three curves, so
-value = realisations per hour = 3600 * steps / (3 * elapsed) (exact when steps is a
-multiple of 3; a single step measures the middle-cost beta).
+Timed region: the whole beta = 10 curve, one library call (both parity-block chains,
+2 x 81 = 162 chain points, each ending in a synchronising overlap).  A step is one of
+`--steps` consecutive segments of those chain points (about 8 of them at the default 20
+steps); the library reports each chain point through its progress callback, which dates
+the step boundaries.  `--warmup` W runs the first ceil(81 W / steps) t points of the same
+curve beforehand.  value = realisations per hour = 3600 / (3 x curve seconds): beta = 10 is
+the middle of the three curves in cost (the longest propagations have |z| = |it -+ beta/4|).
 
 Printed: one JSON line with the roofline of the dominant kernel (apply_H), taken from
 HIP-event timings of every apply_H launch in the timed region, and cpu_baseline = the
 oracle's matrix-free row evaluation timed on a bounded sample, scaled by the
 term-amplitudes one realisation needs.
 
-Also reported, outside the timed region:
+Secondary legs, outside the timed region, each run only while its estimated cost fits in
+the wall budget (`--budget`, seconds from start, default 420), in this order:
 * mixed_precision: the same realisation, Haar state and beta = 10 evaluated with
   complex128 states at t = 0, 5, 10, 20, and the complex64 curve's deviation from it
-  there (the error of the mixed-precision path, per result);
+  there (the error of the mixed-precision path, per result); it also times the complex64
+  path on the same four points, giving the speed ratio over the plain complex128 path at
+  equal OTOC accuracy;
+* serving: the request engine under a Poisson stream of OTOC requests at a fixed offered
+  rate for a fixed window, with p50/p99 submit-to-finish latency and completed
+  realisations per hour;
 * batched: the persistent batched launch on a sample of the many-small-realisations
   workload (realisations of N uniform in {24, 28, 32}, k uniform in {2, 4, 8}, seed
   3000 + r, 4 Haar states each, complex64, beta = 10, t = 0:0.25:15, Krylov dim 30), with
   realisations per hour;
-* serving: the request engine under a Poisson stream of OTOC requests (N uniform in
-  {32, 36, 40, 44, 48}, k uniform in {1, 2, 4, 8}, beta = 10, t = 0:0.5:5, complex64,
-  one Haar state, request seed 50000 + id) at a fixed offered rate for a fixed window,
-  with p50/p99 submit-to-finish latency and completed realisations per hour.
-
 * apply_k1: apply_H at N = 56 with k = 1 (K = 56), where HBM bandwidth binds, with its
   algorithmic HBM fraction;
-* derived figures of the timed curve: the VALU-floor fraction of apply_H (one lane
-  instruction per term-amplitude), the measured HBM rate (hardware-counter bytes over the
-  event-timed launch), and the algorithmic HBM fraction of a whole Lanczos iteration (7
-  vector passes: x read, y written and v_{j-1}, v_j read by the fused epilogue, then y,
-  u_j read and u_{j+1} written by the residual pass);
-* lyapunov_pipeline: disorder averages at N = 14, 22, 30 (128 realisations each, beta = 5,
-  k = 4), crossing times at F0 = 0.75 and 0.85 and the Eq. (5) / Eq. (6) fits: the analysis
-  pipeline end to end and its cost, not a Table I estimate;
 * cpu_baseline.plain_cpu_lanczos: a plain C/OpenMP complex128 matrix-free Lanczos
   iteration on the same block (oracle/cpu_lanczos.c), projected to realisations/hour;
-* mixed_precision also times the complex64 path on the same four points, giving the
-  speed ratio over the plain complex128 path at equal OTOC accuracy.
 * other_entry_points: the Green function of chi_55 on the benchmark realisation (beta = 10,
   t = 0:0.25:5), one dense-SYK apply_H at N = 38 (K = 73815), and a transverse-field Ising
-  chain on 27 qubits as a general spin operator (one apply_H, one e^{-iH} propagation).
+  chain on 27 qubits as a general spin operator (one apply_H, one e^{-iH} propagation);
+* lyapunov_pipeline: disorder averages at N = 14, 22, 30 (128 realisations each, beta = 5,
+  k = 4), crossing times at F0 = 0.75 and 0.85 and the Eq. (5) / Eq. (6) fits: the analysis
+  pipeline end to end and its cost, not a Table I estimate.
+Derived figures of the timed curve: the VALU-floor fraction of apply_H (one lane
+instruction per term-amplitude), the measured HBM rate (hardware-counter bytes over the
+event-timed launch), and the algorithmic HBM fraction of a whole Lanczos iteration (7
+vector passes: x read, y written and v_{j-1}, v_j read by the fused epilogue, then y, u_j
+read and u_{j+1} written by the residual pass).
 
---pmc-sample runs a short chain (one beta, t = 0, 0.25, 0.5) in the identical launch
-configuration plus a 1 GiB device copy, for hardware-counter passes.
+--pmc-sample runs a short chain (t = 0, 0.25, 0.5) in the identical launch configuration
+plus a 1 GiB device copy, for hardware-counter passes.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
+
+T_START = time.perf_counter()
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 N, K_SPARSITY, SEED, STATE_SEED = 56, 4, 56, 5600
-BETAS = (10.0, 5.0, 20.0)
+BETAS = (5.0, 10.0, 20.0)
+BETA_TIMED = 10.0
+CHAIN_POINTS = 2 * 81                     # parity-block chains x t points of one curve
 M_KRYLOV = 60
 TOL_C64 = 3e-6
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3          # published, counts packed FP32 (two lanes per FMA issue)
+FP32_NONPACKED_PEAK_TFLOPS = 78.6        # one FP32 FMA per lane per clock (packed FP32 is disabled here)
+SERVING_WINDOW_S, SERVING_DRAIN_S = 30.0, 45.0
 
 # HBM traffic of one apply_H launch of this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
 # plain device copy of known size (profiles/apply_h_tiled_N56_k4_c64_traffic.txt).  Valid
 # only for the kernel revision it was measured on.
 TRAFFIC = {"kernel_rev": "tiled-block-10", "variant": 10, "fetch_bytes": 27854690717, "write_bytes": 1073876551}
+
+
+def log(msg):
+    print(f"[bench {time.perf_counter() - T_START:6.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def t_grid():
@@ -325,7 +339,7 @@ def batched_leg(syk, n_real=512, seed=3000):
             "mix": "N in {24,28,32}, k in {2,4,8}, seed 3000+r, 4 Haar states, c64, beta=10, t=0:0.25:15, m=30"}
 
 
-def serving_leg(syk, rate_hz=4.0, window_s=30.0, drain_s=60.0, seed=500):
+def serving_leg(syk, rate_hz=4.0, window_s=SERVING_WINDOW_S, drain_s=SERVING_DRAIN_S, seed=500):
     """Poisson stream of OTOC requests into the engine (continuous batching)."""
     import numpy as np
     rng = np.random.default_rng(seed)
@@ -354,8 +368,7 @@ def serving_leg(syk, rate_hz=4.0, window_s=30.0, drain_s=60.0, seed=500):
             done += 1
             failed += r["status"] != 0
             if done % 25 == 0:
-                print(f"[bench] serving: {done}/{len(arrivals)} requests done, {now:.0f} s", file=sys.stderr,
-                      flush=True)
+                log(f"serving: {done}/{len(arrivals)} requests done, {now:.0f} s")
     wall = time.perf_counter() - start
     st = eng.stats()
     eng.close()
@@ -370,19 +383,26 @@ def serving_leg(syk, rate_hz=4.0, window_s=30.0, drain_s=60.0, seed=500):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--budget", type=float, default=420.0,
+                    help="wall seconds from start within which the secondary legs must end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip every secondary leg except cpu_baseline")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU only: realisations of the sparse-SYK OTOC are independent jobs "
               "and shard across GPUs with no communication; run one process per GPU with --gpus 1",
               file=sys.stderr)
+        sys.exit(2)
+    if not 1 <= args.steps <= CHAIN_POINTS or args.warmup < 0:
+        print(f"--steps must lie in [1, {CHAIN_POINTS}] (a step is a segment of one OTOC curve's "
+              f"{CHAIN_POINTS} chain points) and --warmup must be >= 0", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -396,9 +416,10 @@ def main():
     # one-time setup outside the timed region: plans for every kernel variant, autotuning
     variant, variant_ms = syk.autotune(h, syk.C64, stream=stream)
     plan = syk.plan_describe(h, 0, syk.C64, -1)
+    log(f"setup done: variant {variant}, {min(m for m in variant_ms if m > 0):.3f} ms per apply")
 
     if args.pmc_sample:
-        raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, BETAS[0], [0.0, 0.25, 0.5], state_seed=STATE_SEED,
+        raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, BETA_TIMED, [0.0, 0.25, 0.5], state_seed=STATE_SEED,
                                     dtype=syk.C64, m=M_KRYLOV, tol=TOL_C64, profile=True, stream=stream)
         x = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
         x.zero_()
@@ -411,43 +432,51 @@ def main():
         return
 
     ts = t_grid()
+    K_steps = args.steps
+    # step s ends at chain point bounds[s] (chain points are counted 1..CHAIN_POINTS)
+    bounds = [round((s + 1) * CHAIN_POINTS / K_steps) for s in range(K_steps)]
 
-    def curve(beta, profile):
-        t_start = time.perf_counter()
+    if args.warmup:
+        # W steps' worth of chain points: the first ceil(nt * W / K) t points, both blocks
+        n_warm = min(len(ts), max(1, math.ceil(len(ts) * args.warmup / K_steps)))
+        syk.otoc(h, N - 1, N - 2, BETA_TIMED, ts[:n_warm], nvec=1, state_seed=STATE_SEED, dtype=syk.C64,
+                 m=M_KRYLOV, tol=TOL_C64, stream=stream)
+        log(f"warmup done ({n_warm} t points, both blocks)")
 
-        def progress(done, total):
-            if done % 9 == 0 or done == total:
-                print(f"[bench] beta={beta:g}: {done}/{total} chain t-points, {time.perf_counter() - t_start:.0f} s",
-                      file=sys.stderr, flush=True)
-        return syk.otoc(h, N - 1, N - 2, beta, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64, m=M_KRYLOV,
-                        tol=TOL_C64, profile=profile, progress=progress, stream=stream)
+    stamps = []
+    t0 = None
 
-    for w in range(args.warmup):
-        curve(BETAS[w % 3], False)
+    def progress(done, total):
+        now = time.perf_counter()
+        stamps.append(now)
+        k = len(stamps)
+        if k in bounds:
+            s = bounds.index(k)
+            log(f"step {s + 1}/{K_steps} done ({k}/{total} chain points, {now - t0:.1f} s)")
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    results = []
-    for s in range(args.steps):
-        beta = BETAS[s % 3]
-        results.append((beta, curve(beta, True)))
+    raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, BETA_TIMED, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64,
+                                m=M_KRYLOV, tol=TOL_C64, profile=True, progress=progress, stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    curve10 = (raw, nrm, im)
+    ends = [stamps[b - 1] for b in bounds]
+    step_s = [e - s for s, e in zip([t0] + ends[:-1], ends)]
 
-    stats = [r[1][3] for r in results]
-    apply_ms = sum(st["apply_ms"] for st in stats)
-    launches = sum(st["apply_launches"] for st in stats)
-    matvecs = sum(st["matvecs"] for st in stats)
     K = info["K"]
     n = info["block_dim"]
-    avg_s = apply_ms / 1e3 / max(launches, 1)
+    launches = st["apply_launches"]
+    avg_s = st["apply_ms"] / 1e3 / max(launches, 1)
+    matvecs = st["matvecs"]
     term_amps = K * n
     flops = 4.0 * term_amps                   # complex amplitude times real coefficient: 2 FMA
     alg_bytes = 2.0 * n * 8                   # read x once, write y once (complex64)
     achieved_tflops = flops / avg_s / 1e12
-    value = 3600.0 * args.steps / (3.0 * elapsed)
-    t_iter = elapsed / max(matvecs, 1)                      # wall time per Lanczos iteration
-    valu_floor_s = term_amps / 3.93e13                      # one VALU lane-instruction per term-amp
-    term_amps_per_real = 3.0 * matvecs / args.steps * term_amps
+    value = 3600.0 / (3.0 * elapsed)          # a realisation is three curves; beta = 10 is the middle one
+    t_iter = elapsed / max(matvecs, 1)        # wall time per Lanczos iteration
+    valu_floor_s = term_amps / 3.93e13        # one VALU lane-instruction per term-amp
+    term_amps_per_real = 3.0 * matvecs * term_amps
     lib_rev = syk.kernel_revision()
     traffic = None
     if TRAFFIC["fetch_bytes"] and TRAFFIC["kernel_rev"] == lib_rev and TRAFFIC["variant"] == variant:
@@ -458,19 +487,26 @@ def main():
         "value": value,
         "unit": "realisations/h",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": K_steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": elapsed / K_steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "sparse SYK OTOC realisation: N=56, q=4, k=4 (K=224), complex64 states, "
-                               "double Lanczos reductions, Krylov dim 60, tol 3e-6, beta in {5,10,20}, t=0:0.25:20, "
-                               "1 Haar state, W=chi_55, V=chi_54; one step = one beta curve",
-                   "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "krylov_tol": TOL_C64, "betas": list(BETAS), "nt": len(ts),
-                   "betas_timed": [b for b, _ in results], "parallelism": "single GPU"},
+        "config": {"workload": "sparse SYK OTOC, mixed precision at scale: N=56, q=4, k=4 (K=224), seed 56, "
+                               "complex64 states with double Lanczos reductions and tridiagonal exponential, "
+                               "Krylov dim 60, tol 3e-6, t=0:0.25:20, 1 Haar state (seed 5600), W=chi_55, "
+                               "V=chi_54; timed: the whole beta=10 curve (2 parity-block chains x 81 t points = "
+                               f"{CHAIN_POINTS} chain points), one step = {CHAIN_POINTS}/steps consecutive chain "
+                               "points; a realisation = the curves at beta 5, 10 and 20, counted as 3x the "
+                               "beta=10 curve",
+                   "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "krylov_tol": TOL_C64,
+                   "beta_timed": BETA_TIMED, "betas_per_realisation": list(BETAS), "nt": len(ts),
+                   "parallelism": "single GPU"},
+        "step_seconds": {"min": min(step_s), "max": max(step_s)},
+        "curve_seconds": elapsed,
         "apply_H_term_amps_per_s": term_amps / avg_s,
         "apply_H_ms": avg_s * 1e3,
         "apply_H_algorithmic_hbm_frac": alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS,
@@ -478,39 +514,52 @@ def main():
         "apply_H_measured_hbm_TBps": (traffic / avg_s / 1e12) if traffic else None,
         "lanczos_iteration_ms": t_iter * 1e3,
         "lanczos_iteration_algorithmic_hbm_frac": 7.0 * n * 8 / t_iter / 1e9 / HBM_PEAK_GBS,
-        "matvecs_per_curve": matvecs / args.steps,
+        "matvecs_per_curve": matvecs,
         "kernel": {"revision": lib_rev, "variant": variant, "variant_ms": variant_ms, "plan": plan},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_VECTOR_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved_tflops / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "apply_h_tiled", "launches_timed": launches},
-        "otoc_F_norm": {str(b): [float(r[1][i]) for i in (4, 20, 40, 80)] for b, r in results},
+                     "frac_of_nonpacked_fp32": achieved_tflops / FP32_NONPACKED_PEAK_TFLOPS,
+                     "algorithmic_hbm_frac": alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS,
+                     "measured_hbm_frac": (traffic / avg_s / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "kernel": "apply_h_tiled", "launches_timed": launches,
+                     "per_launch": {"term_amps": term_amps, "flop": flops, "algorithmic_bytes": alg_bytes}},
+        "otoc_F_norm": {str(ts[i]): float(nrm[i]) for i in (4, 20, 40, 80)},
     }
-    c10 = [r for b, r in results if b == 10.0]
-    if not args.no_precision and c10:
-        print("[bench] complex128 reference points", file=sys.stderr, flush=True)
+    log(f"timed curve: {elapsed:.1f} s, {matvecs} matvecs, apply {avg_s * 1e3:.3f} ms; "
+        f"{value:.3f} realisations/h")
+
+    # every leg below runs only if its estimated cost still fits in the wall budget
+    def fits(name, est_s):
+        left = args.budget - (time.perf_counter() - T_START)
+        if est_s > left:
+            rec.setdefault("legs_skipped", []).append(name)
+            log(f"{name}: skipped ({est_s:.0f} s estimated, {left:.0f} s of the budget left)")
+            return False
+        log(f"{name} ({left:.0f} s of the budget left)")
+        return True
+
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(term_amps_per_real, seconds_target=10.0)
+    extras = not args.no_extras
+    if extras and not args.no_precision and fits("mixed_precision", 70):
         syk.release_workspace()
-        rec["mixed_precision"] = mixed_precision_check(syk, c10[0], stream)
+        rec["mixed_precision"] = mixed_precision_check(syk, curve10, stream)
         syk.release_workspace()
-    if not args.no_precision:
-        print("[bench] apply_H at k = 1", file=sys.stderr, flush=True)
+    if extras and not args.no_serving and fits("serving", SERVING_WINDOW_S + SERVING_DRAIN_S + 15):
+        rec["serving"] = serving_leg(syk)
+        syk.release_workspace()
+    if extras and not args.no_batched and fits("batched", 30):
+        rec["batched"] = batched_leg(syk)
+    if extras and not args.no_precision and fits("apply_k1", 20):
         rec["apply_k1"] = apply_k1_leg(syk, stream)
         syk.release_workspace()
-    if not args.no_precision:
-        print("[bench] Green function, dense apply, spin operator", file=sys.stderr, flush=True)
+    if extras and not args.no_cpu_baseline and fits("plain_cpu_lanczos", 45):
+        rec["cpu_baseline"]["plain_cpu_lanczos"] = cpu_lanczos_leg(3.0 * matvecs)
+    if extras and not args.no_precision and fits("other_entry_points", 30):
         rec["other_entry_points"] = next_rows_leg(syk, h, stream)
-    if not args.no_batched:
-        print("[bench] batched leg", file=sys.stderr, flush=True)
-        rec["batched"] = batched_leg(syk)
-    if not args.no_batched:
-        print("[bench] t*(N) and lambda_L pipeline", file=sys.stderr, flush=True)
+    if extras and not args.no_batched and fits("lyapunov_pipeline", 50):
         rec["lyapunov_pipeline"] = lyapunov_leg(syk)
-    if not args.no_serving:
-        print("[bench] serving leg", file=sys.stderr, flush=True)
-        rec["serving"] = serving_leg(syk)
-    if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(term_amps_per_real)
-        print("[bench] plain CPU matrix-free Lanczos", file=sys.stderr, flush=True)
-        rec["cpu_baseline"]["plain_cpu_lanczos"] = cpu_lanczos_leg(3.0 * matvecs / args.steps)
+    rec["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(rec), flush=True)
 
 

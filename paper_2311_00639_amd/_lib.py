@@ -207,11 +207,37 @@ def _stream(stream):
 
 def _dtype_of(t):
     import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("state vectors must be torch tensors")
     if t.dtype == torch.complex64:
         return C64
     if t.dtype == torch.complex128:
         return C128
     raise TypeError("state vectors must be complex64 or complex128")
+
+
+def _vectors(need: int, **tensors) -> int:
+    """Check the state-vector tensors of one call before any pointer reaches the library:
+    torch tensors of one complex dtype, contiguous, each holding at least `need` elements,
+    on a GPU.  Returns the dtype code.  The library sees only raw addresses and sizes, so a
+    short, strided or host tensor would otherwise be read or written out of bounds."""
+    import torch
+    dt = None
+    for name, t in tensors.items():
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        d = _dtype_of(t)
+        if dt is not None and d != dt:
+            raise TypeError(f"{name} must have the dtype of the other vectors of the call")
+        dt = d
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() < need:
+            raise ValueError(f"{name} holds {t.numel()} elements, the call needs {need}")
+    for name, t in tensors.items():
+        if not t.is_cuda:
+            raise TypeError(f"{name} must be on the GPU")
+    return dt
 
 
 class Hamiltonian:
@@ -268,17 +294,27 @@ def apply_H(ham: Hamiltonian, block: int, x, y, nvec: int = 1, ld: int = None, s
     With nvec > 1 the tensors hold nvec vectors of leading dimension ld (elements)."""
     n = (2 if block == FULL else 1) << ham.info()["L"]
     ld = n if ld is None else ld
-    _check(_lib.syk_apply_H(ham.handle, block, _dtype_of(x), _ptr(x), _ptr(y), n, nvec, ld, _stream(stream)))
+    if nvec < 1 or ld < n:
+        raise ValueError("nvec must be >= 1 and ld >= the vector length")
+    dt = _vectors((nvec - 1) * ld + n, x=x, y=y)
+    _check(_lib.syk_apply_H(ham.handle, block, dt, _ptr(x), _ptr(y), n, nvec, ld, _stream(stream)))
 
 
 def haar_state(N: int, state_seed: int, v: int, psi_U, psi_D, stream=None):
-    _check(_lib.syk_haar_state(N, state_seed, v, _dtype_of(psi_U), _ptr(psi_U), _ptr(psi_D), _stream(stream)))
+    """The normalised Haar state number v of the seed, split into its U and D blocks."""
+    if N < 6 or N % 2:
+        raise ValueError("N must be even and >= 6")
+    dt = _vectors(1 << (N // 2 - 1), psi_U=psi_U, psi_D=psi_D)
+    _check(_lib.syk_haar_state(N, state_seed, v, dt, _ptr(psi_U), _ptr(psi_D), _stream(stream)))
 
 
 def apply_majorana(N: int, n: int, src_block: int, x, y, scale: complex = 1.0, stream=None):
+    if N < 6 or N % 2:
+        raise ValueError("N must be even and >= 6")
     amps = 1 << (N // 2 - 1)
     sc = complex(scale)
-    _check(_lib.syk_apply_majorana(N, n, src_block, _dtype_of(x), _ptr(x), _ptr(y), amps, sc.real, sc.imag,
+    dt = _vectors(amps, x=x, y=y)
+    _check(_lib.syk_apply_majorana(N, n, src_block, dt, _ptr(x), _ptr(y), amps, sc.real, sc.imag,
                                    _stream(stream)))
 
 
@@ -291,7 +327,8 @@ def default_krylov_opts(dtype: int) -> KrylovOpts:
 def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None, tol: float = None,
                 reorth: int = None, max_substeps: int = None, stream=None) -> dict:
     """out = e^{z H_block} v.  Returns the Krylov statistics as a dict."""
-    dt = _dtype_of(v)
+    n = (2 if block == FULL else 1) << ham.info()["L"]
+    dt = _vectors(n, v=v, out=out)
     o = default_krylov_opts(dt)
     if m is not None:
         o.m = m
@@ -303,7 +340,6 @@ def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None,
         o.max_substeps = max_substeps
     st = KrylovStats()
     z = complex(z)
-    n = (2 if block == FULL else 1) << ham.info()["L"]
     _check(_lib.syk_krylov_expm(ham.handle, block, dt, z.real, z.imag, _ptr(v), _ptr(out), n, ct.byref(o),
                                 ct.byref(st), _stream(stream)))
     return {f: getattr(st, f) for f, _ in KrylovStats._fields_}

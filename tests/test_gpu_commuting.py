@@ -1,0 +1,134 @@
+"""GPU parity at a tiled size against the oracle's closed form for pairwise commuting terms.
+
+When every pair of the realisation's 4-subsets shares 0 or 2 Majoranas, the gamma products
+P_b commute, e^{zH} is the product of the factors cosh(z J_b / 4) + sinh(z J_b / 4) P_b, and
+the random-state OTOC of a Majorana pair (i, j) lying in one term a and in no other reduces to
+-(1/4) <psi| e^{-beta H_rest} (cos(J_a t) + i sin(J_a t) P_a) |psi>  (oracle/commuting.py,
+pinned there against the dense eigendecomposition and the dense chain).  H then has up to
+2^K distinct levels, so a Krylov basis started from a random state keeps growing: these
+checks reach Lanczos dimensions of 16 and more on the path the N = 56 benchmark runs (the
+tiled apply with the fused, lazily normalised Lanczos step and its recombination scales),
+which the K = 1 closed forms (dimension 2) cannot.
+
+Realisations (N = 40, 2^19-amplitude blocks, tiled kernel), found by drawing seeds on the
+oracle side: K = 6, seed 91 with the pair (39, 5); K = 8, seed 188076 with (39, 19).
+
+Tolerances (stated targets): propagator 1e-10 relative in complex128, 1e-5 in complex64;
+F_norm 1e-9 absolute in complex128, 1e-5 with complex64 states; raw F and Im F to the same
+bounds relative to |F_raw(0)| (raw values carry the e^{-beta H} weights of the state).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2311_00639_amd as syk  # noqa: E402
+from oracle import commuting, ensemble, haar  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+N = 40
+REALISATIONS = [(6, 91, 39, 5), (8, 188076, 39, 19)]
+N_VARIANTS = 14
+
+
+def _realisation(K, seed):
+    subs, J, _ = ensemble.sample_terms(N, K / N, seed)
+    h = syk.create_hamiltonian(N, 4, K / N, seed)
+    T = h.terms()
+    assert [tuple(int(a) for a in r) for r in T["ijkl"]] == [tuple(s) for s in subs]
+    assert np.array_equal(T["J"], np.asarray(J))
+    assert commuting.all_commute(subs)
+    return subs, J, h
+
+
+def _dev(a, dt):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(
+        dtype=torch.complex64 if dt == syk.C64 else torch.complex128, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("real", range(len(REALISATIONS)))
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_krylov_expm_full_space_vs_commuting_closed_form(real, dt):
+    """e^{zH} v on the full space (U block then D block, each its own fused Lanczos run) for
+    real, imaginary and complex z; the Krylov dimension of one run reaches 16 or more."""
+    K, seed, _, _ = REALISATIONS[real]
+    subs, J, h = _realisation(K, seed)
+    psi = haar.haar_state(N, 100 + real, 0)
+    vd = _dev(psi, dt)
+    vr = _host(vd)                                   # the rounded input the GPU sees
+    tol = 1e-10 if dt == syk.C128 else 1e-5
+    longest = 0
+    for z in (-9.0j, -2.5, 1.2 - 6.0j):
+        out = torch.empty_like(vd)
+        st = syk.krylov_expm(h, syk.FULL, z, vd, out, m=40)
+        ref = commuting.expm_apply(N, subs, J, z, vr)
+        err = _rel(_host(out), ref)
+        print(f"K={K} dt={dt} z={z}: rel err {err:.2e}, {st}")
+        assert err <= tol, (z, err, st)
+        longest = max(longest, st["matvecs"] / st["substeps"])      # Lanczos vectors per sub-step
+    assert longest >= 16, longest
+
+
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+@pytest.mark.parametrize("variant", range(N_VARIANTS))
+def test_fused_lanczos_step_every_variant_vs_closed_form(dt, variant):
+    """Every tiled kernel variant, pinned, runs the fused Lanczos step of one block (D here,
+    the other half of the full-space vector) for |z| large enough that one sub-step holds
+    more than 16 Lanczos vectors; against the closed form restricted to that block."""
+    K, seed, _, _ = REALISATIONS[1]
+    subs, J, h = _realisation(K, seed)
+    syk.select_variant(h, dt, variant)
+    n = 1 << (N // 2 - 1)
+    psi = haar.haar_state(N, 300 + variant, 0)
+    psi[:n] = 0.0                                    # D block only: e^{zH} keeps the parity
+    vd = _dev(psi[n:], dt)
+    vr = _host(vd)
+    z = 0.4 - 7.0j
+    out = torch.empty_like(vd)
+    st = syk.krylov_expm(h, syk.BLOCK_D, z, vd, out, m=40)
+    full = np.concatenate([np.zeros(n, dtype=np.complex128), vr])
+    ref = commuting.expm_apply(N, subs, J, z, full)
+    assert np.abs(ref[:n]).max() == 0.0
+    err = _rel(_host(out), ref[n:])
+    assert err <= (1e-10 if dt == syk.C128 else 1e-5), (err, st)
+    assert st["matvecs"] >= 16 * st["substeps"], st
+
+
+@pytest.mark.parametrize("real", range(len(REALISATIONS)))
+@pytest.mark.parametrize("beta", [0.0, 4.0])
+@pytest.mark.parametrize("dt", [syk.C128, syk.C64])
+def test_otoc_chain_vs_commuting_closed_form(real, beta, dt):
+    """The whole OTOC chain at N = 40 on the default path (planner layout, autotuned
+    variant, fused Lanczos step); complex64 runs the benchmark's propagation settings
+    (Krylov dimension 60, tolerance 3e-6)."""
+    K, seed, i, j = REALISATIONS[real]
+    subs, J, h = _realisation(K, seed)
+    ts = [0.0, 0.5, 1.7, 4.0, 9.0]
+    ss = 7 + real
+    F = commuting.otoc_state(N, subs, J, i, j, beta, ts, haar.haar_state(N, ss, 0))
+    ref_raw, ref_im = F.real, F.imag
+    ref_nrm = ref_raw / ref_raw[0]
+    if dt == syk.C128:
+        raw, nrm, im, st = syk.otoc(h, i, j, beta, ts, state_seed=ss, dtype=dt, m=40)
+        tol = 1e-9
+    else:
+        raw, nrm, im, st = syk.otoc(h, i, j, beta, ts, state_seed=ss, dtype=dt, m=60, tol=3e-6)
+        tol = 1e-5
+    scale = abs(ref_raw[0])
+    print(f"K={K} beta={beta} dt={dt}: |dF_norm| {np.abs(nrm - ref_nrm).max():.2e}, "
+          f"|dF_raw|/F0 {np.abs(raw - ref_raw).max() / scale:.2e}, matvecs {st['matvecs']}")
+    assert np.abs(nrm - ref_nrm).max() <= tol
+    assert np.abs(raw - ref_raw).max() <= tol * scale
+    assert np.abs(im - ref_im).max() <= tol * scale
+    if beta == 0.0:
+        assert abs(raw[0] + 0.25) <= (1e-12 if dt == syk.C128 else 1e-6)

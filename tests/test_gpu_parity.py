@@ -453,7 +453,7 @@ def test_otoc_config_N16_vs_oracle(i, j, beta, dt):
     g_raw, g_nrm, g_im, st = syk.otoc(h, i, j, beta, ts, nvec=1, state_seed=1001, dtype=dt, m=30)
     tol = 1e-9 if dt == syk.C128 else 1e-5
     assert np.abs(g_raw - raw).max() <= tol
-    assert np.abs(g_nrm - nrm).max() <= tol / abs(raw[0]) * 2
+    assert np.abs(g_nrm - nrm).max() <= tol
     assert np.abs(g_im - im).max() <= tol
     assert st["matvecs"] > 0
 
@@ -505,10 +505,10 @@ def test_otoc_rotated_layout_matches_standard_N40(dt):
     a = syk.otoc(h, 39, 38, 3.0, ts, state_seed=2, dtype=dt, m=30, layout=-1)
     b = syk.otoc(h, 39, 38, 3.0, ts, state_seed=2, dtype=dt, m=30, layout=0)
     c = syk.otoc(h, 39, 38, 3.0, ts, state_seed=2, dtype=dt, m=30, layout=7)
-    tol = 1e-9 if dt == syk.C128 else 2e-5
+    tol = 1e-9 if dt == syk.C128 else 1e-5
     for other in (b, c):
         assert np.abs(a[0] - other[0]).max() <= tol * max(1.0, np.abs(a[0]).max())
-        assert np.abs(a[1] - other[1]).max() <= tol * 10
+        assert np.abs(a[1] - other[1]).max() <= tol
 
 
 def test_otoc_beta0_t0_minus_quarter_N40():

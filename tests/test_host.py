@@ -376,3 +376,36 @@ def test_gather_kernel_groups_terms_by_x_mask():
             d = syk.plan_describe(h, blk, syk.C64, -1)
             assert d["tiled"] == 0 and d["n_groups"] == masks
         assert (h.info()["K"] >= 10 * masks) == dense
+
+
+def test_binding_refuses_bad_vectors_before_the_library():
+    """The binding checks every state-vector tensor (dtype, agreement of dtypes, contiguity,
+    length, device) before a pointer reaches the library: no kernel ever sees a short,
+    strided, mismatched or host buffer."""
+    import torch
+    h = syk.create_hamiltonian(12, 4, 3, 1)
+    n = 1 << 5
+    good = torch.zeros(n, dtype=torch.complex64)                     # right shape, but on the host
+    with pytest.raises(TypeError, match="GPU"):
+        syk.apply_H(h, 0, good, good.clone())
+    with pytest.raises(ValueError, match="elements"):
+        syk.apply_H(h, 0, good, torch.zeros(n - 1, dtype=torch.complex64))
+    with pytest.raises(ValueError, match="elements"):
+        syk.apply_H(h, 0, torch.zeros(2, n, dtype=torch.complex64), torch.zeros(2, n, dtype=torch.complex64),
+                    nvec=2, ld=n + 8)                                # (nvec - 1) ld + n > 2 n
+    with pytest.raises(TypeError, match="dtype"):
+        syk.apply_H(h, 0, good, torch.zeros(n, dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        syk.apply_H(h, 0, good, torch.zeros(n, dtype=torch.float32))
+    with pytest.raises(ValueError, match="contiguous"):
+        syk.apply_H(h, 0, good, torch.zeros(2 * n, dtype=torch.complex64)[::2])
+    with pytest.raises(ValueError, match="elements"):
+        syk.krylov_expm(h, syk.FULL, -1j, good, good.clone())        # the full space needs 2^(N/2)
+    with pytest.raises(TypeError, match="GPU"):
+        syk.krylov_expm(h, 0, -1j, good, good.clone())
+    with pytest.raises(ValueError, match="elements"):
+        syk.haar_state(12, 1, 0, good, torch.zeros(3, dtype=torch.complex64))
+    with pytest.raises(TypeError, match="dtype"):
+        syk.apply_majorana(12, 3, 0, good, torch.zeros(n, dtype=torch.complex128))
+    with pytest.raises(TypeError, match="torch tensor"):
+        syk.apply_majorana(12, 3, 0, good, 12345)
