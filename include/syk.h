@@ -132,6 +132,18 @@ syk_status syk_apply_H(const syk_ham *h, syk_block blk, syk_dtype dt, const void
 syk_status syk_haar_state(int N, uint64_t state_seed, int v, syk_dtype dt,
                           void *psi_U, void *psi_D, void *stream);
 
+/* The same state as syk_haar_state, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * this entry point calls no hipMalloc, hipFree or allocating library routine.  Its norm
+ * partial sums (at most 2049 doubles for N <= 64) live in a fixed device array of 4096
+ * doubles (32 KiB) that each device holds from library load until the process ends.
+ * The call is asynchronous on `stream` (no synchronisation); the array keeps the last
+ * call's partial sums, and calls that overlap on one device (other streams or threads)
+ * race on it, so the caller orders them.  Same arguments and errors as syk_haar_state;
+ * EINVAL also if a size needed more scratch than the array holds. */
+syk_status syk_haar_state_noalloc(int N, uint64_t state_seed, int v, syk_dtype dt,
+                                  void *psi_U, void *psi_D, void *stream);
+
 /* ---------------------------------------------------------------- Majorana insertion
  * y = scale * (gamma_n)_{dst,src} x, the block of gamma_n mapping block `src` to the other
  * block (supplement Sec. I: Majoranas are block off-diagonal).  n <= N-2: the block is A_n

@@ -35,6 +35,7 @@ from ._lib import (  # noqa: F401
     crossing_time,
     green,
     haar_state,
+    haar_state_noalloc,
     kernel_revision,
     krylov_expm,
     library_path,

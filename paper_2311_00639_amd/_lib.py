@@ -135,6 +135,7 @@ _SIGS = {
     "syk_get_terms": [_vp, ct.c_size_t, _vp, _vp, _vp, _vp, _vp, _vp],
     "syk_apply_H": [_vp, _i, _i, _vp, _vp, _u64, _i, _u64, _vp],
     "syk_haar_state": [_i, _u64, _i, _i, _vp, _vp, _vp],
+    "syk_haar_state_noalloc": [_i, _u64, _i, _i, _vp, _vp, _vp],
     "syk_apply_majorana": [_i, _i, _i, _i, _vp, _vp, _u64, _d, _d, _vp],
     "syk_krylov_expm": [_vp, _i, _i, _d, _d, _vp, _vp, _u64, ct.POINTER(KrylovOpts), ct.POINTER(KrylovStats), _vp],
     "syk_otoc": [_vp, _i, _i, _d, _dp, _i, ct.POINTER(OtocOpts), _dp, _dp, _dp, ct.POINTER(OtocStats), _vp],
@@ -306,6 +307,15 @@ def haar_state(N: int, state_seed: int, v: int, psi_U, psi_D, stream=None):
         raise ValueError("N must be even and >= 6")
     dt = _vectors(1 << (N // 2 - 1), psi_U=psi_U, psi_D=psi_D)
     _check(_lib.syk_haar_state(N, state_seed, v, dt, _ptr(psi_U), _ptr(psi_D), _stream(stream)))
+
+
+def haar_state_noalloc(N: int, state_seed: int, v: int, psi_U, psi_D, stream=None):
+    """haar_state through the entry point that allocates no device memory (its partial sums
+    sit in the library's fixed device scratch); asynchronous on the stream."""
+    if N < 6 or N % 2:
+        raise ValueError("N must be even and >= 6")
+    dt = _vectors(1 << (N // 2 - 1), psi_U=psi_U, psi_D=psi_D)
+    _check(_lib.syk_haar_state_noalloc(N, state_seed, v, dt, _ptr(psi_U), _ptr(psi_D), _stream(stream)))
 
 
 def apply_majorana(N: int, n: int, src_block: int, x, y, scale: complex = 1.0, stream=None):

@@ -304,6 +304,35 @@ syk_status syk_haar_state(int N, uint64_t state_seed, int v, syk_dtype dt, void 
     });
 }
 
+syk_status syk_haar_state_noalloc(int N, uint64_t state_seed, int v, syk_dtype dt, void *psi_U, void *psi_D,
+                                  void *stream) {
+    return guarded([&] {
+        check_N(N);
+        require(psi_U && psi_D && psi_U != psi_D, "psi_U, psi_D must be distinct non-NULL buffers");
+        require(v >= 0, "v must be >= 0");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        check_device();
+        const uint64_t n = block_amps(N);
+        const int np = syk::reduction_blocks(n);
+        // the partials and their total live in the fixed scratch; every partial is written
+        // by haar_raw before reduce_partials reads it, so nothing needs clearing
+        double *part = syk::fixed_scratch(static_cast<size_t>(np) + 1);
+        double *sum = part + np;
+        hipStream_t s = as_stream(stream);
+        if (dt == SYK_C64) {
+            syk::launch_haar_raw<float>(state_seed, v, N / 2 - 1, 0, static_cast<float *>(psi_U),
+                                        static_cast<float *>(psi_D), part, np, s);
+            syk::launch_reduce_partials(part, np, 1, sum, s);
+            syk::launch_scale_pair<float>(static_cast<float *>(psi_U), static_cast<float *>(psi_D), n, sum, s);
+        } else {
+            syk::launch_haar_raw<double>(state_seed, v, N / 2 - 1, 0, static_cast<double *>(psi_U),
+                                         static_cast<double *>(psi_D), part, np, s);
+            syk::launch_reduce_partials(part, np, 1, sum, s);
+            syk::launch_scale_pair<double>(static_cast<double *>(psi_U), static_cast<double *>(psi_D), n, sum, s);
+        }
+    });
+}
+
 syk_status syk_apply_majorana(int N, int n, syk_block src, syk_dtype dt, const void *x, void *y, uint64_t n_amps,
                               double scale_re, double scale_im, void *stream) {
     return guarded([&] {

@@ -237,5 +237,9 @@ void launch_multi_dot_partials(const T *basis, uint64_t stride, int nb, const T 
                                int n_part, hipStream_t s);
 
 int reduction_blocks(uint64_t n);   // number of partials the reduction launchers produce
+// this device's copy of the library's fixed device scratch (at least n_doubles doubles;
+// EINVAL beyond its size); looked up once per device, never allocated
+double *fixed_scratch(size_t n_doubles);
+size_t fixed_scratch_doubles();
 
 }  // namespace syk

@@ -6,6 +6,9 @@
 // partials are combined in a fixed order by reduce_partials, so results are repeatable.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace syk {
@@ -217,6 +220,35 @@ void launch_scale_pair(T *a, T *b, uint64_t n, const double *norm2_dev, hipStrea
                        reinterpret_cast<V2<T> *>(b), n, norm2_dev);
     SYK_HIP(hipGetLastError());
 }
+
+// ------------------------------------------------------------------ fixed scratch
+// Device memory of the allocation-free Haar entry point: the per-workgroup partial sums of
+// the norm and their total.  Each device holds its own copy of this array (at its own
+// address) from module load until the process ends; every call on a device reuses it, so
+// calls that overlap on one device race.  Host code must use the address returned by
+// hipGetSymbolAddress on that device, never the array's name.
+constexpr size_t kScratchDoubles = 4096;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+double *fixed_scratch(size_t n_doubles) {
+    if (n_doubles > kScratchDoubles)
+        fail(SYK_EINVAL, "request needs " + std::to_string(n_doubles) + " doubles of fixed scratch, more than the " +
+                             std::to_string(kScratchDoubles) + " available");
+    int dev = 0;
+    SYK_HIP(hipGetDevice(&dev));
+    static std::mutex mu;
+    static std::map<int, double *> ptrs;     // device ordinal -> that device's copy of the array
+    std::lock_guard<std::mutex> g(mu);
+    auto it = ptrs.find(dev);
+    if (it != ptrs.end()) return it->second;
+    void *p = nullptr;
+    SYK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) fail(SYK_EDEVICE, "hipGetSymbolAddress returned no address for the fixed scratch");
+    ptrs[dev] = static_cast<double *>(p);
+    return static_cast<double *>(p);
+}
+
+size_t fixed_scratch_doubles() { return kScratchDoubles; }
 
 // ------------------------------------------------------------------ Majorana insertion
 // dst[m] = s * (-1)^{popc((m ^ x) & z)} * src[m ^ x],  s complex (phase i^w folded in).
