@@ -351,7 +351,7 @@ def serving_leg(syk, rate_hz=4.0, window_s=SERVING_WINDOW_S, drain_s=SERVING_DRA
         if t > window_s:
             break
         arrivals.append((t, int(rng.choice(Ns)), int(rng.choice(ks))))
-    eng = syk.Engine(max_active=4)
+    eng = syk.Engine(budget_bytes=64 << 30, max_active=4)
     start = time.perf_counter()
     done, i, failed = 0, 0, 0
     while done < len(arrivals):

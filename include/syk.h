@@ -187,12 +187,14 @@ void syk_krylov_default_opts(syk_dtype dt, syk_krylov_opts *o);
  * estimate ||v|| beta_j |[e^{tau z T_j} e_1]_j|; a step ends early once the estimate
  * meets the tolerance for the remaining tau, else the largest tau that meets it is taken
  * and the propagation restarts from the result.  beta_j ~ 0 is an invariant subspace
- * (exact result).  v, out: device, n_amps = 2^L; out == v allowed.  stats may be NULL.
+ * (exact result).  v, out: device, n_amps = 2^L, 16-byte aligned; out == v allowed.
+ * stats may be NULL.
  * SYK_FULL (n_amps = 2^(L+1)): the two halves are propagated separately (e^{zH} is block
  * diagonal), each to the tolerance relative to its own norm; the statistics are summed
  * (breakdown: either half).
  * Uses a library-owned device workspace of (m + 2) vectors, reused across calls.
- * Errors: EINVAL, ENOMEM, EDEVICE, ENOTCONV (max_substeps exceeded), ENUMERIC. */
+ * Errors: EINVAL (also for a misaligned v or out), ENOMEM, EDEVICE, ENOTCONV (max_substeps
+ * exceeded), ENUMERIC. */
 syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double z_re, double z_im,
                            const void *v, void *out, uint64_t n_amps, const syk_krylov_opts *o,
                            syk_krylov_stats *stats, void *stream);
@@ -214,6 +216,11 @@ typedef struct {
                               tiled apply_H variants and keep the fastest (syk_autotune) */
     syk_progress_fn progress;   /* optional (NULL = none) */
     void *progress_ctx;
+    int precision_check;   /* 1: with complex64 states, evaluate F again at t = 0 and at the
+                              last t with complex128 states on the same Haar vectors (the
+                              complex128 default tolerance, the same m) and report the
+                              deviation in stats.mp_err; needs the complex128 workspace
+                              (syk_workspace_bytes with SYK_C128).  Ignored for SYK_C128. */
 } syk_otoc_opts;
 
 typedef struct {
@@ -223,6 +230,10 @@ typedef struct {
     double max_err_est;    /* largest per-propagation relative error estimate */
     double apply_ms;       /* profile = 1: summed event-timed duration of apply_H launches */
     long long apply_launches;
+    double mp_err;         /* precision_check = 1: error of the complex64 result against the
+                              complex128 re-evaluation, max(|F_raw(0) - F_raw128(0)| / |F_raw128(0)|,
+                              |F_norm(t_last) - F_norm128(t_last)|); -1 if not evaluated */
+    double mp_seconds;     /* wall time of that re-evaluation (not part of `seconds`) */
 } syk_otoc_stats;
 
 /* Regularised OTOC of Eq. (2) with W = chi_i, V = chi_j (0-based; the paper uses
@@ -414,6 +425,9 @@ typedef struct {
     int m;                 /* Krylov dimension wanted (0 = 30) */
     int m_min;             /* lowest dimension accepted under memory pressure (0 = min(m, 8)) */
     double tol;            /* per-propagation tolerance (<= 0: the dtype's default) */
+    int precision_check;   /* 1: report the complex64 result's error against complex128 in
+                              stats.mp_err (as syk_otoc_opts.precision_check; the footprint then
+                              holds the complex128 workspace) */
 } syk_request;
 
 typedef struct {

@@ -51,7 +51,7 @@ PROGRESS_FN = ct.CFUNCTYPE(None, ct.c_void_p, ct.c_int, ct.c_int)
 class OtocOpts(ct.Structure):
     _fields_ = [("nvec", ct.c_int), ("state_seed", ct.c_uint64), ("dtype", ct.c_int), ("krylov", KrylovOpts),
                 ("profile", ct.c_int), ("layout", ct.c_int), ("autotune", ct.c_int),
-                ("progress", PROGRESS_FN), ("progress_ctx", ct.c_void_p)]
+                ("progress", PROGRESS_FN), ("progress_ctx", ct.c_void_p), ("precision_check", ct.c_int)]
 
 
 class PlanDesc(ct.Structure):
@@ -63,7 +63,8 @@ class PlanDesc(ct.Structure):
 
 class OtocStats(ct.Structure):
     _fields_ = [("matvecs", ct.c_longlong), ("substeps", ct.c_longlong), ("seconds", ct.c_double),
-                ("max_err_est", ct.c_double), ("apply_ms", ct.c_double), ("apply_launches", ct.c_longlong)]
+                ("max_err_est", ct.c_double), ("apply_ms", ct.c_double), ("apply_launches", ct.c_longlong),
+                ("mp_err", ct.c_double), ("mp_seconds", ct.c_double)]
 
 
 class EngineOpts(ct.Structure):
@@ -74,7 +75,7 @@ class Request(ct.Structure):
     _fields_ = [("N", ct.c_int), ("k", ct.c_double), ("seed", ct.c_uint64), ("i", ct.c_int), ("j", ct.c_int),
                 ("beta", ct.c_double), ("t", ct.POINTER(ct.c_double)), ("nt", ct.c_int), ("nvec", ct.c_int),
                 ("state_seed", ct.c_uint64), ("dtype", ct.c_int), ("m", ct.c_int), ("m_min", ct.c_int),
-                ("tol", ct.c_double)]
+                ("tol", ct.c_double), ("precision_check", ct.c_int)]
 
 
 class ResultInfo(ct.Structure):
@@ -357,10 +358,11 @@ def krylov_expm(ham: Hamiltonian, block: int, z: complex, v, out, m: int = None,
 
 def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_seed: int = 0, dtype: int = C128,
          m: int = None, tol: float = None, reorth: int = None, profile: bool = False, layout: int = -1,
-         autotune: bool = True, progress=None, stream=None):
+         autotune: bool = True, progress=None, precision_check: bool = False, stream=None):
     """Regularised OTOC (Eq. (2)) by the random-state estimator.  Returns
     (F_raw, F_norm, F_imag, stats) with numpy float64 arrays.  progress(done, total) is
-    called after each t point of each chain."""
+    called after each t point of each chain.  precision_check (complex64): stats["mp_err"]
+    is the result's error against a complex128 re-evaluation at t = 0 and the last t."""
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
     nt = t.size
     o = OtocOpts()
@@ -371,6 +373,7 @@ def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_
     o.profile = 1 if profile else 0
     o.layout = layout
     o.autotune = 1 if autotune else 0
+    o.precision_check = 1 if precision_check else 0
     cb = None
     if progress is not None:
         cb = PROGRESS_FN(lambda ctx, done, total: progress(done, total))
@@ -393,7 +396,7 @@ def otoc(ham: Hamiltonian, i: int, j: int, beta: float, t, nvec: int = 1, state_
 
 def green(ham: Hamiltonian, n: int, beta: float, t, nvec: int = 1, state_seed: int = 0, dtype: int = C128,
           m: int = None, tol: float = None, profile: bool = False, layout: int = -1, autotune: bool = True,
-          stream=None):
+          precision_check: bool = False, stream=None):
     """Green function of chi_n by the random-state estimator (syk_green).  Returns
     (G_raw, G_norm, G_imag, stats); G_norm is the paper's G_R(t) = Re G(t) / G(0)."""
     t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
@@ -406,6 +409,7 @@ def green(ham: Hamiltonian, n: int, beta: float, t, nvec: int = 1, state_seed: i
     o.profile = 1 if profile else 0
     o.layout = layout
     o.autotune = 1 if autotune else 0
+    o.precision_check = 1 if precision_check else 0
     if m is not None:
         o.krylov.m = m
     if tol is not None:
@@ -570,10 +574,12 @@ class Engine:
         self._nt = {}
 
     def submit(self, N: int, k: float, seed: int, beta: float, t, i: int = None, j: int = None, nvec: int = 1,
-               state_seed: int = 0, dtype: int = C64, m: int = 30, m_min: int = 0, tol: float = 0.0) -> int:
+               state_seed: int = 0, dtype: int = C64, m: int = 30, m_min: int = 0, tol: float = 0.0,
+               precision_check: bool = False) -> int:
         t = np.ascontiguousarray(np.asarray(t, dtype=np.float64))
         r = Request(N, float(k), seed, N - 1 if i is None else i, N - 2 if j is None else j, float(beta),
-                    t.ctypes.data_as(_dp), t.size, nvec, state_seed, dtype, m, m_min, float(tol))
+                    t.ctypes.data_as(_dp), t.size, nvec, state_seed, dtype, m, m_min, float(tol),
+                    1 if precision_check else 0)
         rid = ct.c_uint64()
         _check(_lib.syk_engine_submit(self._h, ct.byref(r), ct.byref(rid)))
         self._nt[rid.value] = t.size

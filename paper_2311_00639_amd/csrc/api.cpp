@@ -373,6 +373,8 @@ syk_status syk_krylov_expm(const syk_ham *h, syk_block blk, syk_dtype dt, double
     return guarded([&] {
         if (h && !h->h.hermitian) syk::fail(SYK_EUNSUPPORTED, "Lanczos propagation needs a Hermitian operator");
         require(h && v && out && o, "NULL argument");
+        require(reinterpret_cast<uintptr_t>(v) % 16 == 0 && reinterpret_cast<uintptr_t>(out) % 16 == 0,
+                "v and out must be 16-byte aligned");
         require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D || blk == SYK_FULL, "invalid block");
         require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
         const uint64_t nb = block_amps(h->h.N);

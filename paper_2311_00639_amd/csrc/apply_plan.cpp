@@ -404,15 +404,22 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
 }
 
 template <typename U>
-static U *upload(const std::vector<U> &v) {
+static U *upload(const std::vector<U> &v, DeviceSlab *slab) {
     U *d = nullptr;
     const size_t n = std::max<size_t>(v.size(), 1);
-    SYK_HIP(hipMalloc(reinterpret_cast<void **>(&d), n * sizeof(U)));
+    if (slab)
+        d = static_cast<U *>(slab->take(n * sizeof(U), "apply plan"));
+    else
+        SYK_HIP(hipMalloc(reinterpret_cast<void **>(&d), n * sizeof(U)));
     if (!v.empty()) SYK_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(U), hipMemcpyHostToDevice));
     return d;
 }
 
 void free_plan(ApplyPlan &p) {
+    if (p.in_slab) {
+        p = ApplyPlan{};
+        return;
+    }
     ignore_status(hipFree(p.pi));
     ignore_status(hipFree(p.ranges));
     ignore_status(hipFree(p.meta));
@@ -422,8 +429,9 @@ void free_plan(ApplyPlan &p) {
     p = ApplyPlan{};
 }
 
-void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out) {
+void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out, DeviceSlab *slab) {
     ApplyPlan p;
+    p.in_slab = slab != nullptr;
     p.bt = bt;
     p.rb = rb;
     p.rot = hp.rot;
@@ -433,13 +441,13 @@ void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out) {
     p.n_pi = hp.n_pi;
     for (size_t i = 0; i < hp.hvec.size() && i < 8; ++i) p.hvec[i] = hp.hvec[i];
     try {
-        p.pi = upload(hp.pi);
-        p.ranges = upload(hp.ranges);
-        p.meta = upload(hp.meta);
-        p.tile_map = upload(hp.tile_map);
+        p.pi = upload(hp.pi, slab);
+        p.ranges = upload(hp.ranges, slab);
+        p.meta = upload(hp.meta, slab);
+        p.tile_map = upload(hp.tile_map, slab);
         std::vector<float> c32(hp.c.begin(), hp.c.end());
-        p.c32 = upload(c32);
-        p.c64 = upload(hp.c);
+        p.c32 = upload(c32, slab);
+        p.c64 = upload(hp.c, slab);
     } catch (...) {
         free_plan(p);
         throw;

@@ -34,7 +34,8 @@ int choose_rotation(const std::vector<BlockTerm> &terms, int L, int bt, int res_
 // offsets in the term records; sr: register-static record form
 HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int rb, int mult, int extra, int s,
                          uint32_t elem_bytes, int res_bits, int sr, int w);
-void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out);
+// device copies of a host plan: hipMalloc'ed, or carved from `slab` when it is not null
+void upload_plan(const HostPlan &hp, int bt, int rb, ApplyPlan &out, DeviceSlab *slab = nullptr);
 void free_plan(ApplyPlan &p);
 
 template <typename T>

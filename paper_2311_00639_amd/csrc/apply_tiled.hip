@@ -512,6 +512,9 @@ void launch_apply_tiled(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_
         SYK_TV(11, 2, 2, 2, 2, 0)
         SYK_TV(10, 2, 2, 4, 2, 0)
         SYK_TV(11, 2, 2, 2, 2, 1)
+        SYK_TV(12, 3, 2, 2, 2, 2)
+        SYK_TV(12, 2, 2, 2, 2, 2)
+        SYK_TV(12, 3, 2, 2, 2, 1)
     } else {
         SYK_TV(12, 2, 2, 1, 0, 0)
         SYK_TV(12, 2, 1, 2, 0, 0)
@@ -527,6 +530,9 @@ void launch_apply_tiled(const ApplyPlan &pl, const T *x, T *y, int nvec, uint64_
         SYK_TV(11, 2, 2, 2, 2, 0)
         SYK_TV(10, 2, 2, 4, 2, 0)
         SYK_TV(11, 2, 2, 2, 2, 1)
+        SYK_TV(11, 2, 2, 2, 2, 2)
+        SYK_TV(11, 1, 2, 2, 2, 2)
+        SYK_TV(10, 1, 2, 4, 2, 2)
     }
 #undef SYK_TV
     fail(SYK_EDEVICE, "unknown tiled apply_H variant");

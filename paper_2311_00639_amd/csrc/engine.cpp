@@ -1,12 +1,20 @@
 // Request engine: continuous batching of OTOC requests on one device.
 //
 // Slots are host worker threads, each with its own HIP stream.  A free slot takes the
-// first queued request (in arrival order) whose device footprint fits in what the budget
-// has left; the oldest request may be overtaken by smaller ones only max_bypass times.
-// Requests admitted while others run share the GPU: their kernels are enqueued on
-// different streams and overlap.  Every request builds its own Hamiltonian (tables and
-// plans on this device), allocates its own workspace and runs the same code path as a
-// single syk_otoc call with autotune off, so its result does not depend on the mix.
+// first queued request (in arrival order) whose device footprint fits in a free region of
+// the engine's arena; the oldest request may be overtaken by smaller ones only max_bypass
+// times.  Requests admitted while others run share the GPU: their kernels are enqueued on
+// different streams and overlap.  Every request builds its own Hamiltonian and runs the
+// same code path as a single syk_otoc call with autotune off, so its result does not
+// depend on the mix.
+//
+// Device memory: the arena is one allocation made when the engine starts (the whole
+// budget).  An admitted request gets one region of it, sized by an upper bound of
+// everything the request puts on the device: its workspace (Krylov basis, chain vectors,
+// reduction partials) and its term tables and apply plans, which are carved from the
+// region instead of allocated.  The region goes back to the arena after the request's
+// stream has drained, so no hipMalloc or hipFree runs while requests are active (hipFree
+// would wait for the whole device and stall the other requests' streams).
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -19,6 +27,7 @@
 #include <thread>
 #include <vector>
 
+#include "apply_plan.hpp"
 #include "engine.hpp"
 #include "krylov.hpp"
 #include "otoc.hpp"
@@ -29,13 +38,89 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-uint64_t footprint_bytes(int N, double k, int m, syk_dtype dt) {
-    const uint64_t n = 1ULL << (N / 2 - 1);
-    const size_t e = (dt == SYK_C64) ? sizeof(float) : sizeof(double);
-    const uint64_t K = static_cast<uint64_t>(std::floor(k * N + 0.5));
-    // workspace + per-block term tables and tiled plans (tile map, records, groups)
-    return otoc_workspace_bytes(n, m, e) + 2 * ((n >> 8) + K * 256 + (1u << 16)) + (1u << 20);
+constexpr uint64_t kRegionAlign = 64ULL << 10;     // arena regions start on 64 KiB boundaries
+uint64_t align_up(uint64_t b, uint64_t a) { return (b + a - 1) / a * a; }
+
+// Upper bound of the device bytes of one block's gather tables (runtime.cpp: six arrays of
+// at most K + 1 entries, each piece 256-byte aligned in a slab).
+uint64_t tables_bound(uint64_t K) { return 4 * 4 * (K + 1) + 4 * (K + 1) + 8 * (K + 1) + 6 * 256; }
+
+// Upper bound of the device bytes of one tiled apply plan (apply_plan.cpp) for K terms on
+// 2^L amplitudes, over every compiled variant: at most 2^(L-10) tiles (the smallest tile
+// has 2^10 amplitudes); at most 8 tiles per workgroup, so the partner union has at most
+// 8 K entries, split steps add at most 8 K / 12 more (a control block holds >= 12
+// records), padding to the buffer count and the prefetch entries add at most 8; ranges
+// are 3 words per step and tile; records are a 64-word control block per step or at
+// most 4 + 2 * 8 words per term; coefficients K + 1 floats and doubles.
+uint64_t plan_bound(int L, uint64_t K) {
+    const uint64_t steps = 8 * K + (8 * K + 11) / 12 + 8;
+    const uint64_t tiles = L > 10 ? (1ULL << (L - 10)) : 1;
+    const uint64_t meta = std::max<uint64_t>((steps + 1) * 64 * 4, (K + 1) * 20 * 4);
+    return steps * 4 + steps * 8 * 3 * 4 + meta + tiles * 4 + (K + 1) * 12 + 6 * 256;
 }
+
+uint64_t footprint_bytes(int N, double k, int m, syk_dtype dt, bool precision_check) {
+    const int L = N / 2 - 1;
+    const uint64_t n = 1ULL << L;
+    // the complex128 re-evaluation of a precision check reuses the workspace
+    const size_t e = (dt == SYK_C64 && !precision_check) ? sizeof(float) : sizeof(double);
+    const uint64_t K = static_cast<uint64_t>(std::floor(k * N + 0.5));
+    // workspace, then per block (U, D) the gather tables and up to two plans per precision
+    // (the planner's layout and the standard one)
+    const uint64_t dev = otoc_workspace_bytes(n, m, e) + 2 * (tables_bound(K) + 4 * plan_bound(L, K));
+    return align_up(dev, kRegionAlign);
+}
+
+// First-fit allocator of regions of one device allocation; free ranges are merged with
+// their neighbours when returned.  Host bookkeeping only (the caller holds the engine lock).
+class Arena {
+  public:
+    void init(uint64_t bytes) {
+        size_ = bytes / kRegionAlign * kRegionAlign;
+        if (size_ == 0) fail(SYK_EINVAL, "engine budget below one 64 KiB region");
+        void *p = nullptr;
+        SYK_HIP(hipMalloc(&p, size_));
+        base_ = static_cast<char *>(p);
+        free_[0] = size_;
+    }
+    ~Arena() {
+        if (base_) ignore_status(hipFree(base_));
+    }
+    uint64_t size() const { return size_; }
+    char *base() const { return base_; }
+    // offset of a free region of `bytes` (a multiple of kRegionAlign), or false
+    bool take(uint64_t bytes, uint64_t &off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            off = it->first;
+            const uint64_t rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            return true;
+        }
+        return false;
+    }
+    void give(uint64_t off, uint64_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    char *base_ = nullptr;
+    uint64_t size_ = 0;
+    std::map<uint64_t, uint64_t> free_;   // offset -> bytes
+};
 
 struct Req {
     uint64_t id = 0;
@@ -43,6 +128,7 @@ struct Req {
     std::vector<double> t;
     int m_used = 0;
     uint64_t footprint = 0;
+    uint64_t offset = 0;        // of its arena region (valid while it runs)
     double t_submit = 0, t_start = 0;
     int bypassed = 0;
     std::atomic<int> cancel{0};
@@ -58,6 +144,7 @@ struct Done {
 struct Engine::Impl {
     int dev = 0;
     uint64_t budget = 0, in_use = 0, peak = 0;
+    Arena arena;
     int max_active = 4, max_bypass = 8;
     Clock::time_point t0 = Clock::now();
 
@@ -75,19 +162,18 @@ struct Engine::Impl {
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
-    // caller holds mu
+    // caller holds mu; an admitted request leaves with its arena region taken
     std::shared_ptr<Req> pick() {
         if (pending.empty()) return nullptr;
-        const uint64_t avail = budget - in_use;
         auto &head = pending.front();
-        if (head->footprint <= avail) {
+        if (arena.take(head->footprint, head->offset)) {
             auto r = head;
             pending.pop_front();
             return r;
         }
         if (head->bypassed >= max_bypass) return nullptr;
         for (auto it = pending.begin() + 1; it != pending.end(); ++it) {
-            if ((*it)->footprint <= avail) {
+            if (arena.take((*it)->footprint, (*it)->offset)) {
                 auto r = *it;
                 pending.erase(it);
                 ++head->bypassed;
@@ -115,8 +201,17 @@ struct Engine::Impl {
         d.norm.assign(q.r.nt, 0.0);
         d.imag.assign(q.r.nt, 0.0);
         try {
+            // the request's region: its workspace first, then its tables and plans
+            DeviceSlab slab;
+            slab.base = arena.base() + q.offset;
+            slab.size = q.footprint;
+            const size_t e = (q.r.dtype == SYK_C64 && !q.r.precision_check) ? sizeof(float) : sizeof(double);
+            const size_t ws_bytes = otoc_workspace_bytes(1ULL << (q.r.N / 2 - 1), q.m_used, e);
+            DeviceBuffer ws;
+            ws.adopt(slab.take(ws_bytes, "workspace"), ws_bytes);
             Hamiltonian h;
             build_hamiltonian(h, q.r.N, q.r.k, q.r.seed);
+            h.slab = &slab;
             syk_otoc_opts o{};
             o.nvec = q.r.nvec;
             o.state_seed = q.r.state_seed;
@@ -126,7 +221,7 @@ struct Engine::Impl {
             if (q.r.tol > 0.0) o.krylov.tol = q.r.tol;
             o.layout = -1;
             o.autotune = 0;
-            DeviceBuffer ws;
+            o.precision_check = q.r.precision_check;
             syk_otoc_stats st{};
             const auto c0 = Clock::now();
             otoc_compute(h, q.r.i, q.r.j, q.r.beta, q.t.data(), q.r.nt, o, ws, s, d.raw.data(), d.norm.data(),
@@ -140,6 +235,7 @@ struct Engine::Impl {
             ignore_status(hipStreamSynchronize(s));
         } catch (const std::bad_alloc &) {
             d.info.status = SYK_ENOMEM;
+            ignore_status(hipStreamSynchronize(s));
         } catch (...) {
             d.info.status = SYK_EDEVICE;
             ignore_status(hipStreamSynchronize(s));
@@ -169,9 +265,10 @@ struct Engine::Impl {
                 set_active_changed(before, before + 1);
                 q->t_start = now();
             }
-            Done d = run(*q, s);
+            Done d = run(*q, s);           // returns with the stream drained
             {
                 std::lock_guard<std::mutex> lk(mu);
+                arena.give(q->offset, q->footprint);
                 in_use -= q->footprint;
                 const int before = static_cast<int>(running.size());
                 running.erase(q->id);
@@ -202,7 +299,8 @@ Engine::Engine(const syk_engine_opts &o) : p_(new Impl) {
         SYK_HIP(hipMemGetInfo(&free_b, &total_b));
         budget = static_cast<uint64_t>(0.85 * static_cast<double>(free_b));
     }
-    p_->budget = budget;
+    p_->arena.init(budget);
+    p_->budget = p_->arena.size();
     p_->max_active = o.max_active > 0 ? o.max_active : 4;
     p_->max_bypass = o.max_bypass >= 0 ? o.max_bypass : 8;
     for (int w = 0; w < p_->max_active; ++w) p_->workers.emplace_back([this] { p_->worker(); });
@@ -240,6 +338,7 @@ uint64_t Engine::submit(const syk_request &r) {
     o.krylov.m = m;
     if (r.tol > 0.0) o.krylov.tol = r.tol;
     o.layout = -1;
+    o.precision_check = r.precision_check;
     check_otoc_args(r.N, r.i, r.j, r.beta, r.t, r.nt, o);
     o.krylov.m = m_min;
     check_krylov_opts(o.krylov);
@@ -251,8 +350,9 @@ uint64_t Engine::submit(const syk_request &r) {
     q->m_used = m;
     std::lock_guard<std::mutex> lk(p_->mu);
     if (p_->stop) fail(SYK_EINVAL, "engine is shutting down");
-    while (q->m_used > m_min && footprint_bytes(r.N, r.k, q->m_used, r.dtype) > p_->budget) --q->m_used;
-    q->footprint = footprint_bytes(r.N, r.k, q->m_used, r.dtype);
+    const bool pc = r.precision_check != 0;
+    while (q->m_used > m_min && footprint_bytes(r.N, r.k, q->m_used, r.dtype, pc) > p_->budget) --q->m_used;
+    q->footprint = footprint_bytes(r.N, r.k, q->m_used, r.dtype, pc);
     if (q->footprint > p_->budget) fail(SYK_ENOMEM, "request footprint at m_min exceeds the engine budget");
     q->id = p_->next_id++;
     q->t_submit = p_->now();

@@ -38,7 +38,17 @@ struct BlockTerm {
     bool imag;
 };
 
+// A region of device memory handed out front to back in 256-byte aligned pieces; nothing
+// in it is freed piece by piece (its owner returns the region as a whole).
+struct DeviceSlab {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+    // next piece of `bytes`; ENOMEM naming `what` when the region is exhausted
+    void *take(size_t bytes, const char *what);
+};
+
 struct DeviceTables {            // per device, per block: the gather kernel's term tables
+    bool in_slab = false;        // carved from a DeviceSlab: not freed by the library
     int n_real = 0;              // real-phase terms of the block
     int K = 0;
     // terms grouped by x mask: group g has mask gx[g], real-phase terms [gs[g], gm[g]) and
@@ -79,6 +89,7 @@ uint32_t rotr_bits(uint32_t v, int s, int L);
 uint32_t rotl_bits(uint32_t v, int s, int L);
 
 struct ApplyPlan {
+    bool in_slab = false;            // device arrays carved from a DeviceSlab: not freed by the library
     int bt = 0, rb = 0, rot = 0, variant = 0, w = 0;
     uint32_t n_tiles = 0;            // output tiles
     uint32_t n_wg = 0;               // workgroups (n_tiles >> w)
@@ -124,6 +135,9 @@ struct Hamiltonian {
     std::vector<BlockTerm> block_terms[2];   // kernel order: real first, then imaginary
     int n_real[2] = {0, 0};
 
+    // where device tables and plans come from: hipMalloc (null) or a slab that outlives the
+    // handle (the request engine carves each request's tables from its arena)
+    DeviceSlab *slab = nullptr;
     std::mutex dev_mu;
     std::vector<DeviceTables> dev[2];  // indexed by device ordinal
     // plans keyed by (block, double?, device, rotation, variant)
@@ -154,12 +168,16 @@ class DeviceBuffer {
     DeviceBuffer &operator=(const DeviceBuffer &) = delete;
     void ensure(size_t bytes);
     void release();
+    // use caller-owned device memory of `bytes` instead of allocating: ensure() then never
+    // allocates (ENOMEM beyond `bytes`) and release() only forgets the pointer
+    void adopt(void *p, size_t bytes);
     char *ptr() const { return p_; }
     size_t size() const { return n_; }
 
   private:
     char *p_ = nullptr;
     size_t n_ = 0;
+    bool owned_ = true;
 };
 
 // per-(device, thread) cached workspace used by the convenience entry points

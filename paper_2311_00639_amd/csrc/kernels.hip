@@ -491,28 +491,63 @@ void launch_scale_copy(const T *src, T *dst, uint64_t n, double scale, hipStream
     SYK_HIP(hipGetLastError());
 }
 
-// out[i] = sum_k coef[k] basis[k][i], coef complex double (re, im interleaved)
+// 16 bytes of complex amplitudes per lane (two complex64 or one complex128): the
+// recombination moves whole 16-byte units so each wave reads or writes 1 KiB per
+// instruction, with kUnroll basis vectors in flight per thread.
+template <typename T> struct Wide;
+template <> struct Wide<float> { using type = float4; static constexpr int amps = 2; };
+template <> struct Wide<double> { using type = double2; static constexpr int amps = 1; };
+constexpr int kUnroll = 4;
+
+// out[i] = sum_k coef[k] basis[k][i], coef complex double (re, im interleaved); summed in
+// double over 16-byte units of each basis vector, kUnroll vectors in flight per step
+__device__ inline void cmac(double (&acc)[4], double cr, double ci, float4 b) {
+    acc[0] += cr * b.x - ci * b.y;
+    acc[1] += cr * b.y + ci * b.x;
+    acc[2] += cr * b.z - ci * b.w;
+    acc[3] += cr * b.w + ci * b.z;
+}
+__device__ inline void cmac(double (&acc)[4], double cr, double ci, double2 b) {
+    acc[0] += cr * b.x - ci * b.y;
+    acc[1] += cr * b.y + ci * b.x;
+}
+__device__ inline void store_unit(float4 *p, const double (&acc)[4]) {
+    *p = float4{static_cast<float>(acc[0]), static_cast<float>(acc[1]), static_cast<float>(acc[2]),
+                static_cast<float>(acc[3])};
+}
+__device__ inline void store_unit(double2 *p, const double (&acc)[4]) { *p = double2{acc[0], acc[1]}; }
+
 template <typename T>
 __global__ void __launch_bounds__(kBlock) combine_kernel(const V2<T> *__restrict__ basis, uint64_t stride, int nb,
                                                          const double *__restrict__ coef, V2<T> *__restrict__ out,
                                                          uint64_t n) {
-    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+    using W = typename Wide<T>::type;
+    const W *bw = reinterpret_cast<const W *>(basis);
+    W *ow = reinterpret_cast<W *>(out);
+    const uint64_t nw = n / Wide<T>::amps, sw = stride / Wide<T>::amps;
+    for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlock + threadIdx.x; i < nw;
          i += static_cast<uint64_t>(gridDim.x) * kBlock) {
-        double ar = 0.0, ai = 0.0;
-        for (int k = 0; k < nb; ++k) {
-            const V2<T> v = basis[k * stride + i];
-            const double cr = coef[2 * k], ci = coef[2 * k + 1];
-            ar += cr * v.x - ci * v.y;
-            ai += cr * v.y + ci * v.x;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        int k = 0;
+        for (; k + kUnroll <= nb; k += kUnroll) {
+            W b[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) b[u] = bw[(k + u) * sw + i];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) cmac(acc, coef[2 * (k + u)], coef[2 * (k + u) + 1], b[u]);
         }
-        out[i] = V2<T>{static_cast<T>(ar), static_cast<T>(ai)};
+        for (; k < nb; ++k) cmac(acc, coef[2 * k], coef[2 * k + 1], bw[k * sw + i]);
+        store_unit(ow + i, acc);
     }
 }
 
 template <typename T>
 void launch_combine(const T *basis, uint64_t stride, int nb, const double *coef_dev, T *out, uint64_t n,
                     hipStream_t s) {
-    hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_for(n, 2)), dim3(kBlock), 0, s,
+    if (n % Wide<T>::amps != 0 || stride % Wide<T>::amps != 0 || reinterpret_cast<uintptr_t>(basis) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(out) % 16 != 0)
+        fail(SYK_EDEVICE, "combine needs 16-byte aligned vectors of whole 16-byte units");
+    hipLaunchKernelGGL(combine_kernel<T>, dim3(grid_for(n / Wide<T>::amps)), dim3(kBlock), 0, s,
                        reinterpret_cast<const V2<T> *>(basis), stride, nb, coef_dev,
                        reinterpret_cast<V2<T> *>(out), n);
     SYK_HIP(hipGetLastError());

@@ -172,6 +172,7 @@ void check_otoc_args(int N, int i, int j, double beta, const double *t, int nt, 
     require(std::isfinite(beta) && beta >= 0.0, "beta must be finite and >= 0");
     require(o.nvec >= 1, "nvec must be >= 1");
     require(o.autotune == 0 || o.autotune == 1, "autotune must be 0 or 1");
+    require(o.precision_check == 0 || o.precision_check == 1, "precision_check must be 0 or 1");
     require(o.dtype == SYK_C64 || o.dtype == SYK_C128, "invalid dtype");
     require(o.layout >= -1 && o.layout < std::max(N / 2 - 1, 1), "layout must be -1 or a rotation in [0, L)");
     check_krylov_opts(o.krylov);
@@ -189,12 +190,39 @@ void otoc_compute(Hamiltonian &H, int i, int j, double beta, const double *t, in
     if (prepend) ts.insert(ts.begin(), 0.0);
     const uint64_t n = 1ULL << H.L;
     std::vector<std::complex<double>> F;
+    st.mp_err = -1.0;
+    st.mp_seconds = 0.0;
     if (o.dtype == SYK_C64) {
         ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(float)));
         otoc_run<float>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel, kind);
     } else {
         ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(double)));
         otoc_run<double>(H, i, j, beta, ts, o, F, st, ws.ptr(), s, cancel, kind);
+    }
+    if (o.precision_check && o.dtype == SYK_C64) {
+        // the same vectors and chain with complex128 states at t = 0 and the last t
+        const auto c0 = std::chrono::steady_clock::now();
+        std::vector<double> tc{0.0};
+        if (ts.back() > 0.0) tc.push_back(ts.back());
+        syk_otoc_opts o2 = o;
+        o2.dtype = SYK_C128;
+        syk_krylov_default_opts(SYK_C128, &o2.krylov);
+        o2.krylov.m = o.krylov.m;
+        o2.krylov.reorth = o.krylov.reorth;
+        o2.krylov.max_substeps = o.krylov.max_substeps;
+        o2.profile = 0;
+        o2.progress = nullptr;
+        o2.precision_check = 0;
+        std::vector<std::complex<double>> F2;
+        syk_otoc_stats st2{};
+        ws.ensure(otoc_workspace_bytes(n, o.krylov.m, sizeof(double)));
+        otoc_run<double>(H, i, j, beta, tc, o2, F2, st2, ws.ptr(), s, cancel, kind);
+        const double r0 = F2[0].real();
+        double err = std::abs(F[0].real() - r0) / std::abs(r0);
+        if (tc.size() > 1)
+            err = std::max(err, std::abs(F.back().real() / F[0].real() - F2[1].real() / r0));
+        st.mp_err = err;
+        st.mp_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
     }
     const double f0 = F[0].real();
     const int off = prepend ? 1 : 0;

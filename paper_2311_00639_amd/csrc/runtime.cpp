@@ -18,7 +18,21 @@ void hip_check(hipError_t e, const char *what) {
 }
 
 // ------------------------------------------------------------------ device tables
+void *DeviceSlab::take(size_t bytes, const char *what) {
+    const size_t b = (std::max<size_t>(bytes, 1) + 255) & ~static_cast<size_t>(255);
+    if (base == nullptr || b > size - used)
+        fail(SYK_ENOMEM, std::string(what) + ": " + std::to_string(b) + " bytes do not fit in the " +
+                             std::to_string(size - used) + " left of this request's device region");
+    void *p = base + used;
+    used += b;
+    return p;
+}
+
 static void free_tables(DeviceTables &t) {
+    if (t.in_slab) {
+        t = DeviceTables{};
+        return;
+    }
     ignore_status(hipFree(t.gx));
     ignore_status(hipFree(t.gs));
     ignore_status(hipFree(t.gm));
@@ -37,8 +51,12 @@ int gather_groups(const std::vector<BlockTerm> &terms) {
 }
 
 template <typename U>
-static void upload_vec(U *&d, const std::vector<U> &h) {
-    SYK_HIP(hipMalloc(reinterpret_cast<void **>(&d), std::max<size_t>(h.size(), 1) * sizeof(U)));
+static void upload_vec(U *&d, const std::vector<U> &h, DeviceSlab *slab) {
+    const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(U);
+    if (slab)
+        d = static_cast<U *>(slab->take(bytes, "term tables"));
+    else
+        SYK_HIP(hipMalloc(reinterpret_cast<void **>(&d), bytes));
     if (!h.empty()) SYK_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice));
 }
 
@@ -52,6 +70,7 @@ const DeviceTables &Hamiltonian::tables(int blk) {
     if (t.gx) return t;
     const auto &bt = block_terms[blk];
     DeviceTables nt;
+    nt.in_slab = slab != nullptr;
     nt.n_real = n_real[blk];
     nt.K = K;
     if (K > 0) {
@@ -79,12 +98,12 @@ const DeviceTables &Hamiltonian::tables(int blk) {
         }
         gs.push_back(static_cast<uint32_t>(K));
         try {
-            upload_vec(nt.gx, gx);
-            upload_vec(nt.gs, gs);
-            upload_vec(nt.gm, gm);
-            upload_vec(nt.gz, gz);
-            upload_vec(nt.gc32, gc32);
-            upload_vec(nt.gc64, gc64);
+            upload_vec(nt.gx, gx, slab);
+            upload_vec(nt.gs, gs, slab);
+            upload_vec(nt.gm, gm, slab);
+            upload_vec(nt.gz, gz, slab);
+            upload_vec(nt.gc32, gc32, slab);
+            upload_vec(nt.gc64, gc64, slab);
         } catch (...) {
             free_tables(nt);
             throw;
@@ -101,7 +120,8 @@ const std::vector<TiledVariant> &tiled_variants<float>() {
                                                 {12, 2, 4, 3, 1, 0, 0}, {13, 3, 2, 1, 1, 1, 0}, {13, 3, 2, 1, 1, 0, 1},
                                                 {13, 3, 2, 1, 1, 0, 2}, {12, 3, 2, 1, 2, 0, 1}, {13, 3, 2, 1, 1, 2, 0},
                                                 {13, 3, 2, 1, 1, 2, 1}, {13, 3, 2, 1, 1, 2, 2}, {11, 2, 2, 1, 2, 2, 0},
-                                                {10, 2, 2, 1, 4, 2, 0}, {11, 2, 2, 1, 2, 2, 1}};
+                                                {10, 2, 2, 1, 4, 2, 0}, {11, 2, 2, 1, 2, 2, 1}, {12, 3, 2, 1, 2, 2, 2},
+                                                {12, 2, 2, 1, 2, 2, 2}, {12, 3, 2, 1, 2, 2, 1}};
     return v;
 }
 template <>
@@ -110,7 +130,8 @@ const std::vector<TiledVariant> &tiled_variants<double>() {
                                                 {11, 1, 4, 3, 1, 0, 0}, {12, 2, 2, 1, 1, 1, 0}, {12, 2, 2, 1, 1, 0, 1},
                                                 {12, 2, 2, 1, 1, 0, 2}, {11, 2, 2, 1, 2, 0, 1}, {12, 2, 2, 1, 1, 2, 0},
                                                 {12, 2, 2, 1, 1, 2, 1}, {12, 2, 2, 1, 1, 2, 2}, {11, 2, 2, 1, 2, 2, 0},
-                                                {10, 2, 2, 1, 4, 2, 0}, {11, 2, 2, 1, 2, 2, 1}};
+                                                {10, 2, 2, 1, 4, 2, 0}, {11, 2, 2, 1, 2, 2, 1}, {11, 2, 2, 1, 2, 2, 2},
+                                                {11, 1, 2, 1, 2, 2, 2}, {10, 1, 2, 1, 4, 2, 2}};
     return v;
 }
 // Before (or without) autotuning: the first of a preference order (control-block records
@@ -143,7 +164,7 @@ const ApplyPlan &Hamiltonian::plan(int blk, int rot, int variant) {
     if (p.pi) return p;
     HostPlan hp = build_host_plan(block_terms[blk], L, tv.bt, tv.rb, tv.nbuf, tv.pf, rot, 2 * sizeof(T),
                                   resident_bits(tv), tv.sr, tv.w);
-    upload_plan(hp, tv.bt, tv.rb, p);
+    upload_plan(hp, tv.bt, tv.rb, p, slab);
     p.variant = variant;
     return p;
 }
@@ -283,6 +304,9 @@ DeviceBuffer::~DeviceBuffer() { release(); }
 
 void DeviceBuffer::ensure(size_t bytes) {
     if (bytes <= n_) return;
+    if (!owned_)
+        fail(SYK_ENOMEM, "workspace needs " + std::to_string(bytes) + " bytes, its caller-owned region holds " +
+                             std::to_string(n_));
     release();
     void *p = nullptr;
     SYK_HIP(hipMalloc(&p, bytes));
@@ -291,9 +315,17 @@ void DeviceBuffer::ensure(size_t bytes) {
 }
 
 void DeviceBuffer::release() {
-    if (p_) ignore_status(hipFree(p_));
+    if (p_ && owned_) ignore_status(hipFree(p_));
     p_ = nullptr;
     n_ = 0;
+    owned_ = true;
+}
+
+void DeviceBuffer::adopt(void *p, size_t bytes) {
+    release();
+    p_ = static_cast<char *>(p);
+    n_ = bytes;
+    owned_ = false;
 }
 
 namespace {

@@ -55,7 +55,7 @@ MIX = [  # N, k, seed, beta
 
 def test_engine_results_equal_alone_and_in_mix():
     torch.cuda.set_device(0)
-    eng = syk.Engine(max_active=4)
+    eng = syk.Engine(budget_bytes=8 << 30, max_active=4)
     ids = {}
     for (N, k, seed, beta) in MIX:
         ids[eng.submit(N, k, seed, beta, TS, state_seed=7, dtype=syk.C64, m=30)] = (N, k, seed, beta)
@@ -77,6 +77,65 @@ def test_engine_results_equal_alone_and_in_mix():
         print(f"N={N} k={k} beta={beta}: |engine - alone| = {d:.3e}")
         assert d <= 1e-5
         assert np.abs(r["F_norm"] - nrm).max() <= 1e-5
+
+
+def test_engine_serves_N56_beside_small_requests():
+    """The large end of the serving mix: an N = 56 request (two blocks of 2^27 amplitudes,
+    k = 1, complex64, about 35 GiB of Krylov basis and chain vectors) is admitted beside
+    N = 24-40 requests from one arena; each result equals its alone run within 1e-5, and
+    every region goes back to the arena."""
+    torch.cuda.set_device(0)
+    ts = [0.0, 0.5]
+    mix = [(56, 1, 56001, 2.0), (24, 4, 21, 5.0), (32, 2, 22, 1.0), (40, 8, 23, 10.0), (36, 1, 24, 2.0)]
+    budget = 48 << 30
+    eng = syk.Engine(budget_bytes=budget, max_active=4)
+    ids = {}
+    for (N, k, seed, beta) in mix:
+        print(f"[engine] submit N={N} k={k} seed={seed} beta={beta}", flush=True)
+        ids[eng.submit(N, k, seed, beta, ts, state_seed=9, dtype=syk.C64, m=30)] = (N, k, seed, beta)
+    got = drain(eng, len(mix))
+    st = eng.stats()
+    eng.close()
+    assert st["completed"] == len(mix) and st["failed"] == 0
+    assert st["peak_bytes"] <= st["budget_bytes"] <= budget and st["bytes_in_use"] == 0
+    big = next(r for r, v in ids.items() if v[0] == 56)
+    assert got[big]["footprint_bytes"] >= syk.workspace_bytes(56, 30, syk.C64)
+    # the N = 56 request overlapped with at least one other
+    others = [got[r] for r in ids if r != big]
+    assert any(o["t_start"] < got[big]["t_end"] and got[big]["t_start"] < o["t_end"] for o in others)
+    for rid, (N, k, seed, beta) in ids.items():
+        r = got[rid]
+        assert r["status"] == 0 and r["m_used"] == 30
+        h = syk.create_hamiltonian(N, 4, k, seed)
+        raw, nrm, im, _ = syk.otoc(h, N - 1, N - 2, beta, ts, nvec=1, state_seed=9, dtype=syk.C64, m=30,
+                                   autotune=False)
+        h.close()
+        d = max(np.abs(r["F_raw"] - raw).max(), np.abs(r["F_imag"] - im).max())
+        print(f"N={N} k={k} beta={beta}: |engine - alone| = {d:.3e}", flush=True)
+        assert d <= 1e-5
+        assert np.abs(r["F_norm"] - nrm).max() <= 1e-5
+    syk.release_workspace()
+
+
+def test_engine_reports_mixed_precision_error_per_result():
+    """A request with precision_check carries its complex64 error against complex128
+    (stats mp_err, within the 1e-5 bound); its footprint holds the complex128 workspace;
+    one without it reports -1."""
+    torch.cuda.set_device(0)
+    eng = syk.Engine(budget_bytes=2 << 30, max_active=2)
+    a = eng.submit(32, 4, 41, 5.0, TS, state_seed=3, dtype=syk.C64, m=30, precision_check=True)
+    b = eng.submit(28, 2, 42, 5.0, TS, state_seed=3, dtype=syk.C64, m=30)
+    got = drain(eng, 2)
+    eng.close()
+    assert got[a]["status"] == 0 and got[b]["status"] == 0
+    assert 0.0 <= got[a]["stats"]["mp_err"] <= 1e-5
+    assert got[a]["footprint_bytes"] >= syk.workspace_bytes(32, 30, syk.C128)
+    assert got[b]["stats"]["mp_err"] == -1.0
+    h = syk.create_hamiltonian(32, 4, 4, 41)
+    _, _, _, st = syk.otoc(h, 31, 30, 5.0, TS, nvec=1, state_seed=3, dtype=syk.C64, m=30, autotune=False,
+                           precision_check=True)
+    h.close()
+    assert abs(st["mp_err"] - got[a]["stats"]["mp_err"]) <= 1e-9
 
 
 def test_engine_matches_oracle_small_N():
@@ -136,7 +195,7 @@ def test_engine_lowers_krylov_dimension_under_memory_pressure():
 
 def test_engine_cancel_queued_and_running():
     torch.cuda.set_device(0)
-    eng = syk.Engine(max_active=1)
+    eng = syk.Engine(budget_bytes=4 << 30, max_active=1)
     long_t = np.arange(0.0, 40.0, 0.25)
     run_id = eng.submit(40, 4, 1, 10.0, long_t, dtype=syk.C64)
     queued = eng.submit(24, 2, 2, 1.0, TS, dtype=syk.C64)

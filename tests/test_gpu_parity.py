@@ -151,7 +151,7 @@ def test_apply_h_tiled_smallest_sizes(N, dt, blk):
         assert np.all(np.abs(y - yref) <= K * U24 * mag)
 
 
-N_VARIANTS = 14
+N_VARIANTS = 17
 
 
 @pytest.mark.parametrize("dt", [syk.C128, syk.C64])
@@ -538,6 +538,56 @@ def test_otoc_benchmark_configuration_c64_against_c128_N56():
     c = syk.otoc(h, N - 1, N - 2, 0.0, [0.0], state_seed=5600, dtype=syk.C64)
     syk.release_workspace()
     assert abs(c[0][0] + 0.25) <= 1e-6
+
+
+def test_otoc_plain_complex128_configuration_N48():
+    """The plain complex128 single-realisation configuration as configured (N = 48, k = 4,
+    so K = 192, seed 48, Krylov dimension 40, beta = 10, 16 Haar vectors of state seed
+    4800, chi_47 and chi_46) on a short t grid.  Per vector: F(0) at beta = 0 is -1/4
+    exactly (chi_i chi_j chi_i chi_j = -1/4 for any normalised state).  The 16-vector curve
+    at beta = 10 through complex64 states agrees with the complex128 one to the
+    mixed-precision bound 1e-5 on F_norm (and on F_raw relative to |F_raw(0)|)."""
+    N = 48
+    torch.cuda.empty_cache()
+    h = syk.create_hamiltonian(N, 4, 4, 48)
+    assert h.info()["K"] == 192
+    for v in range(16):
+        raw, nrm, im, _ = syk.otoc(h, N - 1, N - 2, 0.0, [0.0], nvec=1, state_seed=4800 + v, dtype=syk.C128, m=40)
+        assert abs(raw[0] + 0.25) <= 1e-12, (v, raw[0])
+        assert abs(im[0]) <= 1e-12
+    ts = [0.0, 0.25, 0.5]
+    b = syk.otoc(h, N - 1, N - 2, 10.0, ts, nvec=16, state_seed=4800, dtype=syk.C128, m=40)
+    syk.release_workspace()
+    a = syk.otoc(h, N - 1, N - 2, 10.0, ts, nvec=16, state_seed=4800, dtype=syk.C64, m=40)
+    syk.release_workspace()
+    h.close()
+    print(f"C2 shape: F_norm c128 {b[1]}, |c64 - c128| {np.abs(a[1] - b[1]).max():.2e}", flush=True)
+    assert np.abs(a[1] - b[1]).max() <= 1e-5
+    assert np.abs(a[0] - b[0]).max() <= 1e-5 * abs(b[0][0])
+    assert b[3]["matvecs"] > 0 and a[3]["matvecs"] > 0
+
+
+@pytest.mark.parametrize("N,k,seed", [(24, 4, 31), (40, 2, 32)])
+def test_otoc_precision_check_reports_the_complex128_deviation(N, k, seed):
+    """precision_check: the complex64 result's error against a complex128 re-evaluation on
+    the same Haar vectors (relative F_raw at t = 0, F_norm at the last t) equals the error
+    against a separate complex128 call, and meets the mixed-precision bound 1e-5; the
+    gather path (N = 24) and the tiled path with the fused Lanczos step (N = 40)."""
+    h = syk.create_hamiltonian(N, 4, k, seed)
+    ts = [0.0, 0.5, 1.5]
+    a = syk.otoc(h, N - 1, N - 2, 4.0, ts, nvec=2, state_seed=77, dtype=syk.C64, m=30, precision_check=True)
+    b = syk.otoc(h, N - 1, N - 2, 4.0, [0.0, ts[-1]], nvec=2, state_seed=77, dtype=syk.C128, m=30)
+    c = syk.otoc(h, N - 1, N - 2, 4.0, ts, nvec=2, state_seed=77, dtype=syk.C64, m=30)
+    syk.release_workspace()
+    h.close()
+    want = max(abs(a[0][0] - b[0][0]) / abs(b[0][0]), abs(a[1][-1] - b[1][-1]))
+    st = a[3]
+    print(f"N={N}: mp_err {st['mp_err']:.3e} (separate c128 call {want:.3e}), {st['mp_seconds']:.2f} s", flush=True)
+    assert abs(st["mp_err"] - want) <= 1e-9
+    assert 0.0 <= st["mp_err"] <= 1e-5
+    assert c[3]["mp_err"] == -1.0                      # not requested: not evaluated
+    assert np.array_equal(a[0], c[0])                 # the check does not change the result
+    assert st["matvecs"] == c[3]["matvecs"]
 
 
 def test_otoc_rejects_bad_arguments():
