@@ -22,7 +22,7 @@ oracle's matrix-free row evaluation timed on a bounded sample, scaled by the
 term-amplitudes one realisation needs.
 
 Secondary legs, outside the timed region, each run only while its estimated cost fits in
-the wall budget (`--budget`, seconds from start, default 420), in this order:
+the wall budget (`--budget`, seconds from start, default 440), in this order:
 * mixed_precision: the same realisation, Haar state and beta = 10 evaluated with
   complex128 states at t = 0, 5, 10, 20, and the complex64 curve's deviation from it
   there (the error of the mixed-precision path, per result); it also times the complex64
@@ -31,6 +31,10 @@ the wall budget (`--budget`, seconds from start, default 420), in this order:
 * serving: the request engine under a Poisson stream of OTOC requests at a fixed offered
   rate for a fixed window, with p50/p99 submit-to-finish latency and completed
   realisations per hour;
+* serving_c5: a burst of ten requests spanning the serving sizes N = 32 ... 64 (N = 64 blocks
+  hold 2^31 amplitudes, 16 GiB per complex64 vector) into an engine whose arena is 85% of
+  free device memory: admission by footprint, the N = 64 request at a reduced Krylov
+  dimension, p50/p99 latency and each request's complex64 error against complex128;
 * batched: the persistent batched launch on a sample of the many-small-realisations
   workload (realisations of N uniform in {24, 28, 32}, k uniform in {2, 4, 8}, seed
   3000 + r, 4 Haar states each, complex64, beta = 10, t = 0:0.25:15, Krylov dim 30), with
@@ -380,12 +384,58 @@ def serving_leg(syk, rate_hz=4.0, window_s=SERVING_WINDOW_S, drain_s=SERVING_DRA
             "mix": "N in {32,36,40,44,48}, k in {1,2,4,8}, beta=10, t=0:0.5:5, c64, m=30, 1 Haar state"}
 
 
+def serving_c5_leg(syk, seed=5005):
+    """A burst of OTOC requests spanning the serving configuration's sizes, N in
+    {32, 40, 48, 56, 60, 64} (N = 64: parity blocks of 2^31 amplitudes, 16 GiB per complex64
+    vector), submitted at once into an engine whose arena is 85% of free device memory, so
+    admission by footprint decides what runs together and the largest requests run at a
+    reduced Krylov dimension.  Short chains (beta = 10, t = 0 and 0.5) keep the burst within
+    a minute; k is 1 at N >= 60 and drawn from {1, 2, 4, 8} below.  Every request asks for
+    its complex64 error against complex128 (precision_check)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    ts = [0.0, 0.5]
+    reqs = []
+    for n_maj in (64, 60, 56, 56, 48, 48, 40, 40, 32, 32):
+        k = 1 if n_maj >= 60 else int(rng.choice([1, 2, 4, 8]))
+        reqs.append((n_maj, k))
+    eng = syk.Engine(budget_bytes=0, max_active=4)
+    t0 = time.perf_counter()
+    ids = {}
+    for i, (n_maj, k) in enumerate(reqs):
+        ids[eng.submit(n_maj, k, 70000 + i, 10.0, ts, state_seed=70000 + i, dtype=syk.C64, m=30, m_min=8,
+                       precision_check=n_maj <= 56)] = (n_maj, k)
+    out = []
+    for _ in reqs:
+        r = eng.poll(300000)
+        if r is None:
+            break
+        n_maj, k = ids[r["id"]]
+        out.append({"N": n_maj, "k": k, "status": r["status"], "m_used": r["m_used"],
+                    "footprint_GiB": r["footprint_bytes"] / 2 ** 30, "latency_s": r["t_end"] - r["t_submit"],
+                    "run_s": r["t_end"] - r["t_start"], "matvecs": r["stats"]["matvecs"],
+                    "mp_err": r["stats"]["mp_err"]})
+        log(f"serving_c5: N={n_maj} k={k} done in {out[-1]['latency_s']:.1f} s (m={r['m_used']})")
+    wall = time.perf_counter() - t0
+    st = eng.stats()
+    eng.close()
+    lat = sorted(o["latency_s"] for o in out if o["status"] == 0)
+    errs = [o["mp_err"] for o in out if o["mp_err"] >= 0]
+    return {"requests": len(reqs), "completed": st["completed"], "failed": st["failed"], "wall_s": wall,
+            "p50_latency_s": st["p50_latency_s"], "p99_latency_s": st["p99_latency_s"],
+            "budget_GiB": st["budget_bytes"] / 2 ** 30, "peak_GiB": st["peak_bytes"] / 2 ** 30,
+            "realisations_per_h": 3600.0 * st["completed"] / wall, "max_mp_err": max(errs) if errs else None,
+            "latency_s_sorted": lat, "per_request": out,
+            "mix": "burst of 10: N 64, 60, 56, 56, 48, 48, 40, 40, 32, 32; k = 1 at N >= 60, else from {1,2,4,8}; "
+                   "beta=10, t=(0, 0.5), c64, m=30 (m_min 8), precision_check at N <= 56"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--budget", type=float, default=420.0,
+    ap.add_argument("--budget", type=float, default=440.0,
                     help="wall seconds from start within which the secondary legs must end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true")
@@ -548,6 +598,9 @@ def main():
     if extras and not args.no_serving and fits("serving", SERVING_WINDOW_S + SERVING_DRAIN_S + 15):
         rec["serving"] = serving_leg(syk)
         syk.release_workspace()
+    if extras and not args.no_serving and fits("serving_c5", 95):
+        rec["serving_c5"] = serving_c5_leg(syk)
+        syk.release_workspace()
     if extras and not args.no_batched and fits("batched", 30):
         rec["batched"] = batched_leg(syk)
     if extras and not args.no_precision and fits("apply_k1", 20):
@@ -557,7 +610,7 @@ def main():
         rec["cpu_baseline"]["plain_cpu_lanczos"] = cpu_lanczos_leg(3.0 * matvecs)
     if extras and not args.no_precision and fits("other_entry_points", 30):
         rec["other_entry_points"] = next_rows_leg(syk, h, stream)
-    if extras and not args.no_batched and fits("lyapunov_pipeline", 50):
+    if extras and not args.no_batched and fits("lyapunov_pipeline", 45):
         rec["lyapunov_pipeline"] = lyapunov_leg(syk)
     rec["wall_s"] = time.perf_counter() - T_START
     print(json.dumps(rec), flush=True)

@@ -23,6 +23,13 @@ matfree    per-row matrix elements of H for sampled rows at any N (no dense matr
 commuting  closed forms for pairwise commuting terms: e^{zH} as a product of cosh/sinh
            factors and the random-state OTOC of a lone Majorana pair, on the full vector
            at any N it fits (Pauli strings applied one tensor axis at a time).
+lyapunov   disorder averages, crossing times t* and the Eq. (5) / Eq. (6) fits of the
+           finite-size-scaling analysis, written out with plain least squares.
+
+One module is a CPU comparator rather than a definition: cpu_lanczos (with its C source
+cpu_lanczos.c) is the plain matrix-free complex128 Lanczos that the benchmark times on the
+host cores beside the GPU library.  It is checked against matfree's row products and is
+never called by the library.
 
 Functions with no pin against the paper or mathematics are marked "parity unpinned"
 in their docstrings; at present there are none.
