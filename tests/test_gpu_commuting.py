@@ -29,7 +29,7 @@ pytestmark = pytest.mark.gpu
 
 N = 40
 REALISATIONS = [(6, 91, 39, 5), (8, 188076, 39, 19)]
-N_VARIANTS = 14
+N_VARIANTS = 17             # compiled tiled-kernel variants per precision (syk_autotune's ms array)
 
 
 def _realisation(K, seed):
@@ -87,6 +87,9 @@ def test_fused_lanczos_step_every_variant_vs_closed_form(dt, variant):
     more than 16 Lanczos vectors; against the closed form restricted to that block."""
     K, seed, _, _ = REALISATIONS[1]
     subs, J, h = _realisation(K, seed)
+    if variant == 0:
+        with pytest.raises(syk.SykError):
+            syk.select_variant(h, dt, N_VARIANTS)       # the list above covers every variant
     syk.select_variant(h, dt, variant)
     n = 1 << (N // 2 - 1)
     psi = haar.haar_state(N, 300 + variant, 0)
