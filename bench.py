@@ -13,8 +13,10 @@ Timed region: the whole beta = 10 curve, one library call (both parity-block cha
 `--steps` consecutive segments of those chain points (about 8 of them at the default 20
 steps); the library reports each chain point through its progress callback, which dates
 the step boundaries.  `--warmup` W runs the first ceil(81 W / steps) t points of the same
-curve beforehand.  value = realisations per hour = 3600 / (3 x curve seconds): beta = 10 is
-the middle of the three curves in cost (the longest propagations have |z| = |it -+ beta/4|).
+curve beforehand.  value = realisations per hour = 3600 / (3 x curve seconds x c), with
+c = 1.027 the measured cost of the beta = 5, 10 and 20 curves together relative to three
+beta = 10 curves (`--all-betas` times the three: beta = 20 costs 9% more than beta = 10,
+beta = 5 1% less; the longest propagations have |z| = |it -+ beta/4|).
 
 Printed: one JSON line with the roofline of the dominant kernel (apply_H), taken from
 HIP-event timings of every apply_H launch in the timed region, and cpu_baseline = the
@@ -80,6 +82,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3          # published, counts packed FP32 (two lanes per FMA issue)
 FP32_NONPACKED_PEAK_TFLOPS = 78.6        # one FP32 FMA per lane per clock (packed FP32 is disabled here)
 SERVING_WINDOW_S, SERVING_DRAIN_S = 30.0, 45.0
+# Cost of a whole realisation (the beta = 5, 10 and 20 curves) relative to three beta = 10 curves,
+# measured with all three curves timed by `bench.py --all-betas` on one MI355X (138.0 s, 139.9 s
+# and 152.8 s; profiles/otoc_realisation_three_curves_N56_k4_c64.txt).  The timed region is
+# the beta = 10 curve; value divides its time by this factor's worth of the other two curves.
+REALISATION_COST_FACTOR = (138.0 + 139.9 + 152.8) / (3 * 139.9)
 
 # HBM traffic of one apply_H launch of this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
@@ -439,6 +446,8 @@ def main():
                     help="wall seconds from start within which the secondary legs must end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pmc-sample", action="store_true")
+    ap.add_argument("--all-betas", action="store_true",
+                    help="time the whole realisation (the beta = 5, 10 and 20 curves) and print their costs")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -479,6 +488,26 @@ def main():
                           "apply_ms_avg": st["apply_ms"] / st["apply_launches"], "copy_bytes": x.numel() * 8,
                           "variant": variant, "plan": plan}), flush=True)
         del x, y
+        return
+
+    if args.all_betas:
+        ts = t_grid()
+        out = {"all_betas": True, "curves": {}}
+        for beta in BETAS:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            raw, nrm, im, st = syk.otoc(h, N - 1, N - 2, beta, ts, nvec=1, state_seed=STATE_SEED, dtype=syk.C64,
+                                        m=M_KRYLOV, tol=TOL_C64, stream=stream)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            out["curves"][str(beta)] = {"seconds": sec, "matvecs": st["matvecs"],
+                                        "F_norm": {str(ts[i]): float(nrm[i]) for i in (20, 40, 80)}}
+            log(f"beta {beta}: {sec:.1f} s, {st['matvecs']} matvecs")
+        tot = sum(c["seconds"] for c in out["curves"].values())
+        out["realisation_seconds"] = tot
+        out["realisations_per_h"] = 3600.0 / tot
+        out["cost_factor_vs_three_beta10"] = tot / (3.0 * out["curves"]["10.0"]["seconds"])
+        print(json.dumps(out), flush=True)
         return
 
     ts = t_grid()
@@ -523,7 +552,7 @@ def main():
     flops = 4.0 * term_amps                   # complex amplitude times real coefficient: 2 FMA
     alg_bytes = 2.0 * n * 8                   # read x once, write y once (complex64)
     achieved_tflops = flops / avg_s / 1e12
-    value = 3600.0 / (3.0 * elapsed)          # a realisation is three curves; beta = 10 is the middle one
+    value = 3600.0 / (3.0 * elapsed * REALISATION_COST_FACTOR)   # a realisation is the three curves
     t_iter = elapsed / max(matvecs, 1)        # wall time per Lanczos iteration
     valu_floor_s = term_amps / 3.93e13        # one VALU lane-instruction per term-amp
     term_amps_per_real = 3.0 * matvecs * term_amps
@@ -550,13 +579,15 @@ def main():
                                "Krylov dim 60, tol 3e-6, t=0:0.25:20, 1 Haar state (seed 5600), W=chi_55, "
                                "V=chi_54; timed: the whole beta=10 curve (2 parity-block chains x 81 t points = "
                                f"{CHAIN_POINTS} chain points), one step = {CHAIN_POINTS}/steps consecutive chain "
-                               "points; a realisation = the curves at beta 5, 10 and 20, counted as 3x the "
-                               "beta=10 curve",
+                               "points; a realisation = the curves at beta 5, 10 and 20, priced as 3x the "
+                               "beta=10 curve times their measured cost factor 1.027",
                    "N": N, "K": K, "block_amps": n, "krylov_m": M_KRYLOV, "krylov_tol": TOL_C64,
                    "beta_timed": BETA_TIMED, "betas_per_realisation": list(BETAS), "nt": len(ts),
                    "parallelism": "single GPU"},
         "step_seconds": {"min": min(step_s), "max": max(step_s)},
         "curve_seconds": elapsed,
+        "realisation_cost_factor": REALISATION_COST_FACTOR,
+        "value_three_beta10_curves": 3600.0 / (3.0 * elapsed),
         "apply_H_term_amps_per_s": term_amps / avg_s,
         "apply_H_ms": avg_s * 1e3,
         "apply_H_algorithmic_hbm_frac": alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS,
