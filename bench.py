@@ -555,7 +555,7 @@ def main():
     value = 3600.0 / (3.0 * elapsed * REALISATION_COST_FACTOR)   # a realisation is the three curves
     t_iter = elapsed / max(matvecs, 1)        # wall time per Lanczos iteration
     valu_floor_s = term_amps / 3.93e13        # one VALU lane-instruction per term-amp
-    term_amps_per_real = 3.0 * matvecs * term_amps
+    term_amps_per_real = 3.0 * matvecs * REALISATION_COST_FACTOR * term_amps   # the three curves' matvecs
     lib_rev = syk.kernel_revision()
     traffic = None
     if TRAFFIC["fetch_bytes"] and TRAFFIC["kernel_rev"] == lib_rev and TRAFFIC["variant"] == variant:
@@ -638,7 +638,7 @@ def main():
         rec["apply_k1"] = apply_k1_leg(syk, stream)
         syk.release_workspace()
     if extras and not args.no_cpu_baseline and fits("plain_cpu_lanczos", 45):
-        rec["cpu_baseline"]["plain_cpu_lanczos"] = cpu_lanczos_leg(3.0 * matvecs)
+        rec["cpu_baseline"]["plain_cpu_lanczos"] = cpu_lanczos_leg(3.0 * matvecs * REALISATION_COST_FACTOR)
     if extras and not args.no_precision and fits("other_entry_points", 30):
         rec["other_entry_points"] = next_rows_leg(syk, h, stream)
     if extras and not args.no_batched and fits("lyapunov_pipeline", 45):
