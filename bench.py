@@ -437,6 +437,42 @@ def serving_c5_leg(syk, seed=5005):
                    "beta=10, t=(0, 0.5), c64, m=30 (m_min 8), precision_check at N <= 56"}
 
 
+def plain_c128_leg(syk, stream):
+    """The plain complex128 single-realisation configuration (N = 48, k = 4 so K = 192, seed 48,
+    16 Haar states of seed 4800, Krylov dimension 40, beta = 10, t = 0:0.25:20, chi_47 and chi_46),
+    timed as one library call in complex128 (tolerance 1e-12) and again with complex64 states
+    (FP64 reductions, tolerance 3e-6) on the same realisation and states: realisations per hour
+    of each and the largest difference of their normalised curves."""
+    import numpy as np
+    n_maj = 48
+    h = syk.create_hamiltonian(n_maj, 4, 4, 48)
+    ts = t_grid()
+    res = {}
+    for dt, name, kw in ((syk.C128, "c128", dict(m=40)), (syk.C64, "c64", dict(m=40, tol=TOL_C64))):
+        syk.autotune(h, dt, stream=stream)
+
+        def progress(done, total, name=name):
+            if done % 256 == 0 or done == total:
+                log(f"plain_c128: {name} {done}/{total} chain points")
+
+        t0 = time.perf_counter()
+        raw, nrm, im, st = syk.otoc(h, n_maj - 1, n_maj - 2, 10.0, ts, nvec=16, state_seed=4800, dtype=dt,
+                                    progress=progress, stream=stream, **kw)
+        sec = time.perf_counter() - t0
+        syk.release_workspace()
+        res[name] = {"seconds": sec, "matvecs": st["matvecs"], "realisations_per_h": 3600.0 / sec,
+                     "F_norm": {str(ts[i]): float(nrm[i]) for i in (20, 40, 80)}, "_nrm": nrm}
+        log(f"plain_c128: {name} {sec:.1f} s, {st['matvecs']} matvecs")
+    err = float(np.abs(res["c64"]["_nrm"] - res["c128"]["_nrm"]).max())
+    for r in res.values():
+        del r["_nrm"]
+    h.close()
+    return {"plain_c128": True, "config": "N=48, k=4 (K=192), seed 48, 16 Haar states (seed 4800), Krylov dim 40, "
+                                          "beta=10, t=0:0.25:20, chi_47 / chi_46",
+            "c128": res["c128"], "c64": res["c64"], "max_abs_err_F_norm_c64_vs_c128": err,
+            "speedup_c64_over_c128": res["c128"]["seconds"] / res["c64"]["seconds"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -448,6 +484,9 @@ def main():
     ap.add_argument("--pmc-sample", action="store_true")
     ap.add_argument("--all-betas", action="store_true",
                     help="time the whole realisation (the beta = 5, 10 and 20 curves) and print their costs")
+    ap.add_argument("--plain-c128", action="store_true",
+                    help="time the plain complex128 single-realisation configuration (N = 48, k = 4, 16 Haar "
+                         "states, Krylov dim 40, beta = 10, t = 0:0.25:20) and the same through complex64")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
@@ -470,6 +509,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.plain_c128:
+        print(json.dumps(plain_c128_leg(syk, stream)), flush=True)
+        return
     h = syk.create_hamiltonian(N, 4, K_SPARSITY, SEED)
     info = h.info()
     # one-time setup outside the timed region: plans for every kernel variant, autotuning
