@@ -58,7 +58,11 @@ vector passes: x read, y written and v_{j-1}, v_j read by the fused epilogue, th
 read and u_{j+1} written by the residual pass).
 
 --pmc-sample runs a short chain (t = 0, 0.25, 0.5) in the identical launch configuration
-plus a 1 GiB device copy, for hardware-counter passes.
+plus a 1 GiB device copy, for hardware-counter passes.  --all-betas times the whole
+realisation (the three curves, about 7 minutes) and prints their costs, the source of the
+pricing factor above.  --plain-c128 times the plain complex128 single-realisation
+configuration (N = 48, 16 Haar states, Krylov dimension 40, beta = 10, t = 0:0.25:20) and the
+same through complex64 states (about 8 minutes).
 """
 import argparse
 import json
