@@ -220,11 +220,13 @@ constexpr int waitcnt_vm(int vm) { return (vm & 15) | (7 << 4) | (15 << 8) | (((
 
 #define SYK_LDS(p) ((__attribute__((address_space(3))) void *)(p))
 
-// Waves that issue the partner copies: at most four.  A wave's LDS reads queue behind the
-// LDS writes of the direct copies it issued itself, so when every wave copies, every wave's
-// term loop waits for the copy; with the copy confined to a few waves the others keep
-// computing while it lands (measured with a probe of this loop shape: copy plus term loop
-// 2.08 against 2.46 us per step when all waves copy, 2.03 for the term loop alone).
+// Fourth dword of a raw buffer descriptor on gfx9-family targets: 32-bit data format, no
+// swizzle, no index stride.
+constexpr uint32_t kBufferWord3 = 0x00020000u;
+
+// Waves that issue the partner copies: the first four (measured on the benchmark block:
+// 7.75 ms per apply with four copying waves against 8.42 with all sixteen, 8.43 with two
+// and 7.93 with eight).
 constexpr int copy_waves(int nt) { return nt / 64 < 4 ? nt / 64 : 4; }
 
 // direct-copy instructions per copying thread for one tile
@@ -234,22 +236,28 @@ constexpr int copy_instrs() {
 }
 
 // Copy partner tile `src` (2^BT amplitudes) into LDS buffer `dst` with direct
-// global-to-LDS loads issued by the first copy_waves() waves: 16 bytes per lane, a wave
-// writes 1 KiB contiguous per instruction, so the LDS holds the tile in index order.  No
-// VGPRs are involved.
+// memory-to-LDS loads (buffer form) issued by the first copy_waves() waves: 16 bytes per
+// lane, a wave writes 1 KiB contiguous per instruction, so the LDS holds the tile in index
+// order.  No VGPRs receive data.  The buffer form, unlike the global form, lets the compiler
+// count the term loop's LDS reads one by one (with a global-form copy in flight it waits for
+// all eight reads of a term before the first FMA).
 template <typename T, int BT, int RB>
 __device__ __forceinline__ void dma_tile(const typename V2t<T>::type *src, typename V2t<T>::type *dst,
                                          uint32_t tid) {
     constexpr uint32_t CT = copy_waves(1 << (BT - RB)) * 64;   // copying threads
     constexpr int PER = copy_instrs<T, BT, RB>();
-    const char *g = reinterpret_cast<const char *>(src);
+    static_assert(PER >= 1 && PER * CT * 16 == (1u << BT) * 2 * sizeof(T), "whole 1 KiB pieces per copying wave");
     char *l = reinterpret_cast<char *>(dst);
     if (tid < CT) {                                              // whole waves: a uniform branch
-        const uint32_t wave_base = (tid & ~63u) * 16u;
+        // one descriptor spanning the tile; the piece offset goes in a scalar register and
+        // only the lane's 16-byte slot in a VGPR
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<typename V2t<T>::type *>(src), 0, (1u << BT) * 2u * sizeof(T), kBufferWord3);
+        const uint32_t wave_base = __builtin_amdgcn_readfirstlane((tid & ~63u) * 16u);
 #pragma unroll
         for (int j = 0; j < PER; ++j)
-            __builtin_amdgcn_global_load_lds(g + (j * CT + tid) * 16, SYK_LDS(l + j * CT * 16 + wave_base), 16, 0,
-                                             0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, SYK_LDS(l + j * CT * 16 + wave_base), 16, tid * 16,
+                                                     j * CT * 16, 0, 0);
     }
 }
 
