@@ -237,10 +237,12 @@ void launch_lanczos_normalize(T *w, const double *beta, uint64_t n, hipStream_t 
 void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_out, double *beta2_out,
                             hipStream_t s);
 // fused path: w <- w - alpha_j s_j u_j (v = u_j, s_j from beta2[j], j >= 1; 1 for j = 0) and
-// per-block partials of ||w||^2 (reduction_blocks(n) of them)
+// ||w||^2 at beta2_out, summed in a fixed order over per-workgroup partials (one workgroup
+// per 256 amplitudes, at most partials_cap of them) and a 512-double stage buffer
 template <typename T>
 void launch_lanczos_residual(T *w, const T *v, const double *alpha, const double *beta2, int j, uint64_t n,
-                             double *partials, hipStream_t s);
+                             double *partials, uint64_t partials_cap, double *stage, double *beta2_out,
+                             hipStream_t s);
 template <typename T>
 void launch_scale_copy(const T *src, T *dst, uint64_t n, double scale, hipStream_t s);
 template <typename T>
