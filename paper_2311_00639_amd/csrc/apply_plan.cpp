@@ -267,13 +267,23 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
     const int tb = bt - rb;
     const uint32_t tmask = (1u << tb) - 1u;
     const uint32_t rmask = (1u << rb) - 1u;
-    std::map<uint32_t, std::vector<int>> byg;
+    std::map<uint32_t, std::vector<int>> byg;   // terms by group, in term order
     for (int a = 0; a < static_cast<int>(terms.size()); ++a) byg[rotr_bits(terms[a].x, s, L) >> bt].push_back(a);
     std::unordered_map<uint32_t, std::array<uint32_t, 3>> range;   // g -> (first, mid, end)
     std::vector<std::array<uint32_t, 5>> compact;                   // sr = 2: per-term block record
+    std::vector<char> plain;                                        // sr = 2: record has xr = zr = 0
     const uint32_t rec_dw = block_record_dwords(elem_bytes), rec_max = block_records(elem_bytes);
+    // sr = 2: within each (group, phase) run the terms that touch no register bit (xr = zr = 0:
+    // partner register r for output register r, no register sign) come first
+    auto is_plain = [&](int a) {
+        const uint32_t x = rotr_bits(terms[a].x, s, L), z = rotr_bits(terms[a].z, s, L);
+        return (((x & low) >> tb) & rmask) == 0 && ((z >> tb) & rmask) == 0;
+    };
     uint32_t count = 0;
-    for (const auto &kv : byg) {
+    for (auto &kv : byg) {
+        if (sr == 2)
+            std::stable_sort(kv.second.begin(), kv.second.end(),
+                             [&](int a, int b) { return is_plain(a) && !is_plain(b); });
         std::array<uint32_t, 3> r{count, 0u, 0u};
         for (int pass = 0; pass < 2; ++pass) {
             if (pass == 1) r[1] = count;
@@ -301,6 +311,7 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
                         std::memcpy(&rec[3], &t.c, 8);
                     }
                     compact.push_back(rec);
+                    plain.push_back(xr == 0 && zr == 0);
                     hp.meta.resize(hp.meta.size() - 3);
                 } else if (sr) {
                     hp.meta.push_back((xr << rb) | zr);        // code of the compiled register path
@@ -381,23 +392,29 @@ HostPlan build_host_plan(const std::vector<BlockTerm> &terms, int L, int bt, int
     if (sr == 2) {
         // one 64-dword control block per partner step (and one more for the last prefetch):
         // lanes rec_dw j .. rec_dw (j + 1) - 1 record j, lane 60 the record counts (tile i: real in bits 8i..8i+3,
-        // imaginary in 8i+4..8i+7), lane 61 the partner offset copied during that step
+        // imaginary in 8i+4..8i+7), lane 62 how many of them lead their run with xr = zr = 0 (same
+        // layout), lane 61 the partner offset copied during that step
         hp.meta.assign(static_cast<size_t>(hp.n_pi + 1) * 64, 0u);
         for (int st = 0; st <= hp.n_pi; ++st) {
             uint32_t *blk = &hp.meta[static_cast<size_t>(st) * 64];
             blk[61] = hp.pi[std::min<size_t>(st + extra, hp.pi.size() - 1)];
             if (st == hp.n_pi) continue;
-            uint32_t j = 0, counts = 0;
+            uint32_t j = 0, counts = 0, plain_counts = 0;
             for (size_t i = 0; i < tpw; ++i) {
                 const uint32_t *r = &hp.ranges[(static_cast<size_t>(st) * tpw + i) * 3];
                 if (r[1] - r[0] > 15 || r[2] - r[1] > 15) fail(SYK_EDEVICE, "control block count overflow");
                 counts |= ((r[1] - r[0]) << (8 * i)) | ((r[2] - r[1]) << (8 * i + 4));
+                uint32_t pre = 0, pim = 0;      // leading plain records of each phase run
+                while (r[0] + pre < r[1] && plain[r[0] + pre]) ++pre;
+                while (r[1] + pim < r[2] && plain[r[1] + pim]) ++pim;
+                plain_counts |= (pre << (8 * i)) | (pim << (8 * i + 4));
                 for (uint32_t a = r[0]; a < r[2]; ++a, ++j) {
                     if (j >= rec_max) fail(SYK_EDEVICE, "control block record overflow");
                     for (uint32_t f = 0; f < rec_dw; ++f) blk[rec_dw * j + f] = compact[a][f];
                 }
             }
             blk[60] = counts;
+            blk[62] = plain_counts;
         }
     }
     return hp;

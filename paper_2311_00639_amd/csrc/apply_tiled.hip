@@ -198,6 +198,44 @@ __device__ __forceinline__ void block_term(typename V2t<T>::type (&acc)[1 << RB]
     }
 }
 
+// A control-block term with xr = zr = 0 (the host puts these first in each run): output
+// register r reads partner register r at a constant LDS offset from one address, with no
+// register sign.
+template <typename T, int BT, int RB, bool IM>
+__device__ __forceinline__ void block_term_plain(typename V2t<T>::type (&acc)[1 << RB],
+                                                 const typename V2t<T>::type *b, uint32_t cur, int j, uint32_t tile,
+                                                 uint32_t tid) {
+    using V = typename V2t<T>::type;
+    constexpr int R = 1 << RB;
+    constexpr int TB = BT - RB;
+    constexpr int RD = sizeof(T) == 4 ? 4 : 5;          // dwords per record
+    const uint32_t w0 = __builtin_amdgcn_readlane(cur, RD * j);
+    const uint32_t w1 = __builtin_amdgcn_readlane(cur, RD * j + 1);
+    const uint32_t w2 = __builtin_amdgcn_readlane(cur, RD * j + 2);
+    const uint32_t w3 = __builtin_amdgcn_readlane(cur, RD * j + 3);
+    T c;
+    if constexpr (sizeof(T) == 4) {
+        c = __uint_as_float(w3);
+    } else {
+        const uint32_t w4 = __builtin_amdgcn_readlane(cur, RD * j + 4);
+        c = __hiloint2double(static_cast<int>(w4), static_cast<int>(w3));
+    }
+    const uint32_t par = (__popc(tile & w2) + __popc(tid & (w1 & 0xffffffu))) & 1u;
+    const T cl = flip_sign(c, par << 31);
+    const V *bs = b + (tid ^ (w0 & 0xffffffu));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const V q = bs[r << TB];
+        if (IM) {
+            acc[r].x -= cl * q.y;
+            acc[r].y += cl * q.x;
+        } else {
+            acc[r].x += cl * q.x;
+            acc[r].y += cl * q.y;
+        }
+    }
+}
+
 // one group's terms (real-phase terms [t0, tm), i-phase terms [tm, t1)) in either record form
 template <typename T, int BT, int RB, int SR>
 __device__ __forceinline__ void group_terms(typename V2t<T>::type (&acc)[1 << RB], const typename V2t<T>::type *b,
@@ -346,14 +384,19 @@ __global__ void __launch_bounds__(1 << (BT - RB), OCC * (1 << (BT - RB)) / 256) 
         uint32_t blk0 = blocks[lane], blk1 = 0;
         auto terms_blk = [&](const V *b, uint32_t cur) __attribute__((always_inline)) {
             const uint32_t cnt = __builtin_amdgcn_readlane(cur, 60);
+            const uint32_t pln = __builtin_amdgcn_readlane(cur, 62);    // leading plain records per run
             int j = 0;
             static_for<0, TPW>([&](auto ic) __attribute__((always_inline)) {
                 constexpr int i = decltype(ic)::value;
                 const uint32_t tile = t0 ^ hs.h[i];
                 const int nre = static_cast<int>((cnt >> (8 * i)) & 15u);
                 const int nim = static_cast<int>((cnt >> (8 * i + 4)) & 15u);
-                for (const int e = j + nre; j < e; ++j) block_term<T, BT, RB, false>(acc[i], b, cur, j, tile, tid);
-                for (const int e = j + nim; j < e; ++j) block_term<T, BT, RB, true>(acc[i], b, cur, j, tile, tid);
+                const int pre = static_cast<int>((pln >> (8 * i)) & 15u);
+                const int pim = static_cast<int>((pln >> (8 * i + 4)) & 15u);
+                for (const int e = j + pre; j < e; ++j) block_term_plain<T, BT, RB, false>(acc[i], b, cur, j, tile, tid);
+                for (const int e = j + nre - pre; j < e; ++j) block_term<T, BT, RB, false>(acc[i], b, cur, j, tile, tid);
+                for (const int e = j + pim; j < e; ++j) block_term_plain<T, BT, RB, true>(acc[i], b, cur, j, tile, tid);
+                for (const int e = j + nim - pim; j < e; ++j) block_term<T, BT, RB, true>(acc[i], b, cur, j, tile, tid);
             });
         };
         for (int k0 = 0; k0 < n_pi; k0 += 2) {
