@@ -96,7 +96,7 @@ REALISATION_COST_FACTOR = (127.8 + 129.6 + 141.6) / (3 * 129.6)
 # passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
 # plain device copy of known size (profiles/apply_h_tiled_N56_k4_c64_traffic.txt).  Valid
 # only for the kernel revision it was measured on.
-TRAFFIC = {"kernel_rev": "tiled-block-13", "variant": 10, "fetch_bytes": 27995983142, "write_bytes": 1073872896}
+TRAFFIC = {"kernel_rev": "tiled-block-14", "variant": 10, "fetch_bytes": 28039795806, "write_bytes": 1073872896}
 
 
 def log(msg):

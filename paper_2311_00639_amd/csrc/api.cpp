@@ -839,6 +839,6 @@ const char *syk_status_string(syk_status s) {
 
 const char *syk_last_error(void) { return g_last_error.c_str(); }
 
-const char *syk_kernel_revision(void) { return "tiled-block-13"; }
+const char *syk_kernel_revision(void) { return "tiled-block-14"; }
 
 }  // extern "C"

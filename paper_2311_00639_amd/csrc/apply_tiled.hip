@@ -267,6 +267,15 @@ constexpr uint32_t kBufferWord3 = 0x00020000u;
 // and 7.93 with eight).
 constexpr int copy_waves(int nt) { return nt / 64 < 4 ? nt / 64 : 4; }
 
+// f(integral_constant<int, i>) for i = I .. N - 1 (compile-time piece index of a copy)
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for_j(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for_j<I + 1, N>(f);
+    }
+}
+
 // direct-copy instructions per copying thread for one tile
 template <typename T, int BT, int RB>
 constexpr int copy_instrs() {
@@ -291,11 +300,16 @@ __device__ __forceinline__ void dma_tile(const typename V2t<T>::type *src, typen
         // only the lane's 16-byte slot in a VGPR
         const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<typename V2t<T>::type *>(src), 0, (1u << BT) * 2u * sizeof(T), kBufferWord3);
-        const uint32_t wave_base = __builtin_amdgcn_readfirstlane((tid & ~63u) * 16u);
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, SYK_LDS(l + j * CT * 16 + wave_base), 16, tid * 16,
-                                                     j * CT * 16, 0, 0);
+        // copying wave w moves the contiguous PER KiB from byte w * PER KiB; four 1 KiB pieces
+        // share one LDS base (M0) and differ by the instruction offset, which the hardware adds
+        // to the memory and the LDS address alike
+        const uint32_t wbase = __builtin_amdgcn_readfirstlane((tid >> 6) * PER * 1024u);
+        const uint32_t lane = tid & 63u;
+        static_for_j<0, PER>([&](auto jc) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc, SYK_LDS(l + wbase + (j / 4) * 4096), 16, lane * 16,
+                                                     wbase + (j / 4) * 4096, (j % 4) * 1024, 0);
+        });
     }
 }
 
