@@ -87,10 +87,10 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3          # published, counts packed FP32 (two la
 FP32_NONPACKED_PEAK_TFLOPS = 78.6        # one FP32 FMA per lane per clock (packed FP32 is disabled here)
 SERVING_WINDOW_S, SERVING_DRAIN_S = 30.0, 45.0
 # Cost of a whole realisation (the beta = 5, 10 and 20 curves) relative to three beta = 10 curves,
-# measured with all three curves timed by `bench.py --all-betas` on one MI355X (122.8 s, 124.5 s
-# and 136.0 s; profiles/otoc_realisation_three_curves_N56_k4_c64.txt).  The timed region is
+# measured with all three curves timed by `bench.py --all-betas` on one MI355X (119.0 s, 120.6 s
+# and 131.8 s; profiles/otoc_realisation_three_curves_N56_k4_c64.txt).  The timed region is
 # the beta = 10 curve; value divides its time by this factor's worth of the other two curves.
-REALISATION_COST_FACTOR = (122.8 + 124.5 + 136.0) / (3 * 124.5)
+REALISATION_COST_FACTOR = (119.0 + 120.6 + 131.8) / (3 * 120.6)
 
 # HBM traffic of one apply_H launch of this workload, from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes over `bench.py --pmc-sample`, each scaled by the same counter's reading for a
