@@ -536,6 +536,21 @@ typedef struct {
 } syk_plan_desc;
 syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, syk_plan_desc *out);
 
+/* Control blocks of that plan (host-only; for inspection and tests), when the variant in use
+ * has record form 2: one 64-word block per partner step plus one for the last prefetch.  In
+ * a block, lanes 4j .. 4j+3 (complex64; 5j .. 5j+4 for complex128) hold record j: the thread
+ * bits of x | (x register bits) << 24, the thread bits of z | (register sign mask) << 24,
+ * z >> tile_bits, and the coefficient (float, or the two words of a double).  Records come
+ * tile by tile, real-phase before i-phase.  Lane 60 counts them (tile i: real in bits
+ * 8i..8i+3, i-phase in 8i+4..8i+7).  Lane 62 counts, in the same layout, the records at the
+ * head of each run that touch no register bit (register bits of x and z zero).  Lane 61 is
+ * the partner offset copied during the step.  Masks are in the plan's layout (rotation rot
+ * of syk_plan_describe).  out: host, cap words (NULL to query the size); *n_words receives the
+ * number of words.  Errors: EINVAL, EUNSUPPORTED (block not tiled, or the variant in use has
+ * no control blocks). */
+syk_status syk_plan_blocks(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, uint32_t *out, size_t cap,
+                           size_t *n_words);
+
 /* Schedule autotuner: time each compiled variant of the tiled apply_H kernel (tile size,
  * LDS buffering, prefetch depth; each in its planned layout) on this Hamiltonian and keep
  * the fastest for the current device and precision.  *variant receives the choice (-1 if

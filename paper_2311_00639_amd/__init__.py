@@ -43,6 +43,7 @@ from ._lib import (  # noqa: F401
     otoc,
     otoc_batch,
     otoc_ensemble,
+    plan_blocks,
     plan_describe,
     release_workspace,
     select_variant,

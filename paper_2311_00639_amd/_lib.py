@@ -144,6 +144,7 @@ _SIGS = {
     "syk_tridiag_expm": [_i, _dp, _dp, _d, _d, _dp, _dp],
     "syk_release_workspace": [],
     "syk_plan_describe": [_vp, _i, _i, _i, ct.POINTER(PlanDesc)],
+    "syk_plan_blocks": [_vp, _i, _i, _i, ct.c_void_p, ct.c_size_t, ct.POINTER(ct.c_size_t)],
     "syk_autotune": [_vp, _i, ct.POINTER(_i), ct.POINTER(ct.c_float), _i, _vp],
     "syk_select_variant": [_vp, _i, _i],
     "syk_op_create": [_i, ct.c_size_t, _vp, _vp, _dp, _dp, ct.POINTER(_vp)],
@@ -538,6 +539,15 @@ def plan_describe(ham: Hamiltonian, block: int, dtype: int, layout: int = -1) ->
     d = PlanDesc()
     _check(_lib.syk_plan_describe(ham.handle, block, dtype, layout, ct.byref(d)))
     return {f: getattr(d, f) for f, _ in PlanDesc._fields_}
+
+
+def plan_blocks(ham: Hamiltonian, block: int, dtype: int, layout: int = -1):
+    """Control blocks of the tiled apply_H plan (host-only): uint32 array (blocks, 64)."""
+    n = ct.c_size_t()
+    _check(_lib.syk_plan_blocks(ham.handle, block, dtype, layout, None, 0, ct.byref(n)))
+    out = np.zeros(n.value, dtype=np.uint32)
+    _check(_lib.syk_plan_blocks(ham.handle, block, dtype, layout, out.ctypes.data, n.value, ct.byref(n)))
+    return out.reshape(-1, 64)
 
 
 def autotune(ham: Hamiltonian, dtype: int, stream=None):

@@ -723,6 +723,31 @@ syk_status syk_tridiag_expm(int n, const double *alpha, const double *beta, doub
     });
 }
 
+syk_status syk_plan_blocks(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, uint32_t *out, size_t cap,
+                           size_t *n_words) {
+    return guarded([&] {
+        require(h && n_words, "NULL argument");
+        require(blk == SYK_BLOCK_U || blk == SYK_BLOCK_D, "invalid block");
+        require(dt == SYK_C64 || dt == SYK_C128, "invalid dtype");
+        auto &H = const_cast<syk::Hamiltonian &>(h->h);
+        require(layout >= -1 && layout < std::max(H.L, 1), "layout must be -1 or a rotation in [0, L)");
+        const bool c64 = dt == SYK_C64;
+        if (!(c64 ? syk::use_tiled<float>(H.L) : syk::use_tiled<double>(H.L)))
+            syk::fail(SYK_EUNSUPPORTED, "the block is not served by the tiled kernel");
+        const int var = c64 ? H.variant<float>() : H.variant<double>();
+        const syk::TiledVariant tv = c64 ? syk::tiled_variants<float>()[var] : syk::tiled_variants<double>()[var];
+        if (tv.sr != 2) syk::fail(SYK_EUNSUPPORTED, "the variant in use has no control blocks");
+        const int rot = layout >= 0 ? layout : (c64 ? H.internal_rotation<float>(var) : H.internal_rotation<double>(var));
+        const syk::HostPlan hp = syk::build_host_plan(H.block_terms[blk], H.L, tv.bt, tv.rb, tv.nbuf, tv.pf, rot,
+                                                      c64 ? 8u : 16u, syk::resident_bits(tv), tv.sr, tv.w);
+        *n_words = hp.meta.size();
+        if (out) {
+            require(cap >= hp.meta.size(), "cap is smaller than the control blocks");
+            std::copy(hp.meta.begin(), hp.meta.end(), out);
+        }
+    });
+}
+
 syk_status syk_plan_describe(const syk_ham *h, syk_block blk, syk_dtype dt, int layout, syk_plan_desc *out) {
     return guarded([&] {
         require(h && out, "NULL argument");

@@ -13,7 +13,7 @@ namespace syk {
 // term group g = pi ^ hvec[i] to tile i, whose records are [first, mid) (real phase) and
 // [mid, end) (i phase) at ranges[(step * 2^w + i) * 3].
 // record form 2: dwords per record (4 + one more for a double coefficient) and records per
-// 64-dword control block (lanes 0..59 hold records, 60 and 61 the counts and next partner)
+// 64-dword control block (lanes 0..59 hold records, 60 and 62 the counts, 61 the next partner)
 inline uint32_t block_record_dwords(uint32_t elem_bytes) { return elem_bytes == 8 ? 4u : 5u; }
 inline uint32_t block_records(uint32_t elem_bytes) { return 60u / block_record_dwords(elem_bytes); }
 
