@@ -444,8 +444,8 @@ void launch_lanczos_scalars(const double *partials, int n_part, double *alpha_ou
 }
 
 // 16 bytes of complex amplitudes per lane (two complex64 or one complex128): the
-// streaming kernels below move whole 16-byte units so each wave reads or writes 1 KiB per
-// instruction.
+// recombination below moves whole 16-byte units so each wave reads or writes 1 KiB per
+// instruction (the residual pass takes one amplitude per thread instead).
 template <typename T> struct Wide;
 template <> struct Wide<float> { using type = float4; static constexpr int amps = 2; };
 template <> struct Wide<double> { using type = double2; static constexpr int amps = 1; };
