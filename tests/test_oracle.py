@@ -710,3 +710,14 @@ def test_commuting_realisations_used_by_the_gpu_tests(N, K, seed, i, j):
     subs, J, _ = ensemble.sample_terms(N, K / N, seed)
     assert len(subs) == K and commuting.all_commute(subs)
     assert commuting.lone_pair_term(subs, i, j) >= 0
+
+
+def test_splitmix64_reference_streams():
+    """The oracle's SplitMix64 reproduces the generator's published reference outputs
+    (tests/golden/splitmix64_reference.txt): seed 0 and seed 1234567, five outputs each."""
+    from oracle.splitmix import SplitMix64
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_reference.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 2
+    for row in rows:
+        g = SplitMix64(int(row[0]))
+        assert [g.next() for _ in range(len(row) - 1)] == [int(v) for v in row[1:]]
