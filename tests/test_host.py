@@ -417,22 +417,27 @@ def _rotr(v, s, L):
     return ((v >> s) | (v << (L - s))) & m if s else v
 
 
-@pytest.mark.parametrize("N,k,blk", [(40, 4.0, 0), (56, 4.0, 0), (56, 8.0, 1)])
-def test_control_blocks_hold_every_term_plain_records_first(N, k, blk):
-    """The control blocks of the benchmark variant (complex64, 2^13-amplitude tiles, 8
-    registers per thread, 4 tiles per workgroup), decoded word by word and compared with
-    the Hamiltonian's own block terms (J, x and z masks, phases): every (tile, term) pair
-    appears once, with its layout-rotated masks, register sign mask and coefficient, in
-    the right phase; the records that touch no register bit lead each run and lane 62
-    counts exactly them."""
+@pytest.mark.parametrize("N,k,blk,dt", [(40, 4.0, 0, "c64"), (56, 4.0, 0, "c64"), (56, 8.0, 1, "c64"),
+                                        (44, 4.0, 0, "c128"), (52, 4.0, 1, "c128")])
+def test_control_blocks_hold_every_term_plain_records_first(N, k, blk, dt):
+    """The control blocks of variant 10 (complex64: 2^13-amplitude tiles, 8 registers per
+    thread; complex128: 2^12-amplitude tiles, 4 registers; 4 tiles per workgroup), decoded
+    word by word and compared with the Hamiltonian's own block terms (J, x and z masks,
+    phases): every (tile, term) pair appears once, with its layout-rotated masks, register
+    sign mask and coefficient, in the right phase; the records that touch no register bit
+    lead each run and lane 62 counts exactly them."""
     import numpy as np
+    code = syk.C64 if dt == "c64" else syk.C128
     h = syk.create_hamiltonian(N, 4, k, N)
-    syk.select_variant(h, syk.C64, 10)
-    d = syk.plan_describe(h, blk, syk.C64, -1)
-    assert d["tiled"] == 1 and d["tile_bits"] == 13 and d["tiles_per_wg"] == 4
-    blocks = syk.plan_blocks(h, blk, syk.C64, -1)
+    syk.select_variant(h, code, 10)
+    d = syk.plan_describe(h, blk, code, -1)
+    bt, rb = (13, 3) if dt == "c64" else (12, 2)
+    assert d["tiled"] == 1 and d["tile_bits"] == bt and d["tiles_per_wg"] == 4
+    blocks = syk.plan_blocks(h, blk, code, -1)
     L = N // 2 - 1
-    bt, rb, tpw, s = 13, 3, 4, d["rot"]
+    tpw, s = 4, d["rot"]
+    rd = 4 if dt == "c64" else 5                  # words per record
+    rec_max = 60 // rd
     tb = bt - rb
     tmask, rmask = (1 << tb) - 1, (1 << rb) - 1
     # expected records from the terms: the coefficient folds J/4, the sign of i^p and the
@@ -444,13 +449,14 @@ def test_control_blocks_hold_every_term_plain_records_first(N, k, blk):
     for a in range(len(T["J"])):
         x, z = int(T["xmask"][a]), int(T["zmask"][a])
         p = (int(phase[a]) + 2 * (bin(x & z).count("1") & 1)) & 3
-        c = np.float32(0.25 * T["J"][a] * (-1.0 if p in (2, 3) else 1.0))
+        cd = 0.25 * T["J"][a] * (-1.0 if p in (2, 3) else 1.0)
+        cw = tuple(int(v) for v in np.frombuffer((np.float32(cd) if dt == "c64" else np.float64(cd)).tobytes(),
+                                                  dtype=np.uint32))
         xr_, zr_ = _rotr(x, s, L), _rotr(z, s, L)
         xr = (xr_ >> tb) & rmask
         zr = (zr_ >> tb) & rmask
         sm = sum(((bin(q & zr).count("1") & 1) << q) for q in range(rmask + 1))
-        key = ((xr_ & tmask) | (xr << 24), (zr_ & tmask) | (sm << 24), zr_ >> bt,
-               int(np.frombuffer(c.tobytes(), dtype=np.uint32)[0]), p & 1)
+        key = ((xr_ & tmask) | (xr << 24), (zr_ & tmask) | (sm << 24), zr_ >> bt) + cw + (p & 1,)
         want[key] = want.get(key, 0) + tpw
         n_plain += tpw if (xr == 0 and zr == 0) else 0
     got = {}
@@ -464,15 +470,15 @@ def test_control_blocks_hold_every_term_plain_records_first(N, k, blk):
                 pre = (pln >> (8 * i + 4 * imag)) & 15
                 assert pre <= n
                 for r in range(n):
-                    w = [int(v) for v in b[4 * j:4 * j + 4]]
+                    w = [int(v) for v in b[rd * j:rd * j + rd]]
                     is_plain = (w[0] >> 24) == 0 and (w[1] >> 24) == 0
                     assert is_plain == (r < pre), (i, imag, r, pre, n)
-                    key = (w[0], w[1], w[2], w[3], imag)
+                    key = tuple(w) + (imag,)
                     got[key] = got.get(key, 0) + 1
                     j += 1
                 plain_total += pre
-        assert j <= 15
-        assert not b[4 * j:60].any()          # nothing after the last record
+        assert j <= rec_max
+        assert not b[rd * j:60].any()         # nothing after the last record
     assert got == want
     assert plain_total == n_plain
     h.close()
