@@ -7,15 +7,17 @@
 // t0 ^ span(h) of the tile index space), held in registers: thread t keeps outputs
 // r * NT + t, r < R, of each.  Terms are grouped on the host by g = x_a >> BT, so every term
 // of a group reads the same partner tile T ^ g.  The workgroup streams the union of its
-// tiles' partner tiles once: each partner tile is copied into LDS by direct global-to-LDS
-// loads (the next one streams into the other buffer while the current one is consumed), and
-// every term that needs it reads it with an XOR-permuted index: the thread bits of x_a
-// permute the lane's LDS address once per term, the register bits give one address per
-// register read.  The tile and thread parts of the sign are folded into the coefficient once
-// per term, the register part is one sign operation per read, so an amplitude costs one LDS
-// read, one address operation, one sign operation and two FMAs.  Term data comes either from
-// per-term records (scalar loads) or from per-step control blocks held in a VGPR and read
-// with readlane (no scalar loads in the term loop).  The host planner (apply_plan.cpp) maps
+// tiles' partner tiles once: each partner tile is copied into LDS by direct memory-to-LDS
+// loads (buffer form, issued by four waves; the next one streams into the other buffer while
+// the current one is consumed), and every term that needs it reads it with an XOR-permuted
+// index: the thread bits of x_a permute the lane's LDS address once per term, the register
+// bits give one address per register read.  The tile and thread parts of the sign are folded
+// into the coefficient once per term, the register part is one sign operation per read, so an
+// amplitude costs one LDS read, one address operation, one sign operation and two FMAs; a term
+// that touches no register bit (the host puts these first in each run) reads at constant
+// offsets and has no register signs.  Term data comes either from per-term records (scalar
+// loads) or from per-step control blocks held in a VGPR and read with readlane (no scalar
+// loads in the term loop).  The host planner (apply_plan.cpp) maps
 // workgroups to tiles so that the tiles resident on one XCD form a coset of a subspace that
 // many partner offsets differ by, and orders partner steps class by class, so a partner tile
 // fetched for one workgroup is re-read from L2 by others.
